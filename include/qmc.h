@@ -1,0 +1,297 @@
+/*
+ * qmc.h -- C ABI of the MI355X (gfx950) quasi-Monte Carlo sampling library.
+ *
+ * Implements the data-parallel core of Keller, Waechter and Binder, "Quasi-Monte Carlo
+ * Algorithms (not only) for Graphics Software" (arXiv 2307.15584): digital sequences
+ * (Sec. 2.3, Eq. ts), rank-1 lattice sequences (Sec. 2.4, Eq. R1LS), randomisation kept
+ * in integers (Sec. 2.1, 2.3, 2.5.2) and the float conversion map_u32_to_unifloat
+ * (Sec. 2.1, Alg. 1), batched over indices and dimensions, and fused into per-pixel
+ * QMC integro-approximation (Sec. 2.5) with an adjoint for parameter gradients.
+ *
+ * Conventions for every call:
+ *   - Pointers marked "device" are HIP device allocations owned by the caller; the
+ *     library never frees, retains or allocates them, and performs no host<->device copy.
+ *     Pointers marked "host" are ordinary host memory, read or written before return.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream of the current
+ *     device) and is asynchronous: results are visible after the stream is synchronised.
+ *     No call synchronises the stream, so every call may be captured in a hipGraph.
+ *   - Arguments are validated on the host before anything is enqueued; a non-OK status
+ *     means nothing was enqueued.  qmc_last_error() then describes the problem.  A fault
+ *     inside a kernel surfaces at the caller's next synchronisation, as a HIP error.
+ *   - Index ranges are 32-bit: first + n <= 2^32 is required (Sec. 2.5 warns that a
+ *     silently wrapping index is hard to find, so a range that would wrap is rejected).
+ *   - Integer samples are u32 fixed-point fractions: value v stands for v * 2^-32.
+ */
+#ifndef QMC_H
+#define QMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QMC_OK = 0,
+    QMC_ERR_INVALID_ARGUMENT = 1, /* null pointer, zero dimension count, bad flags, ld < n, ... */
+    QMC_ERR_OUT_OF_RANGE = 2,     /* index range beyond 2^32, too many dimensions, ...         */
+    QMC_ERR_UNSUPPORTED = 3,      /* a valid request this build does not implement              */
+    QMC_ERR_DEVICE = 4,           /* a HIP runtime call failed                                  */
+    QMC_ERR_WORKSPACE = 5         /* caller-provided workspace too small                        */
+} qmc_status;
+
+/* Opaque per-device state: device properties, tuned launch parameters and captured
+ * graphs.  It holds no caller buffers.  One context may be used from one thread at a time. */
+typedef struct qmc_context_s* qmc_context;
+
+/* A hipStream_t, passed as an untyped handle so that this header needs no HIP headers. */
+typedef void* qmc_stream;
+
+#define QMC_MAX_DIMS 64   /* dimensions per call (s) */
+#define QMC_MAX_DEGREE 16 /* initial direction numbers per dimension */
+
+/* flags */
+#define QMC_SHIFT_XOR 1u        /* shift by XOR (digital shift, Sec. 2.3) instead of addition mod 2^32 */
+#define QMC_LATTICE_BACKWARD 2u /* lattice: enumerate phi_2(2^32-1-i) so the origin comes last (Alg. 4) */
+
+/* ---------------------------------------------------------------- context ---- */
+
+/* Create a context for HIP device `device`.  *out receives the handle.
+ * Errors: INVALID_ARGUMENT (out NULL), DEVICE (no such device / HIP failure). */
+qmc_status qmc_create(int device, qmc_context* out);
+
+/* Destroy a context and everything it owns (tuned parameters, graphs).  NULL is a no-op. */
+qmc_status qmc_destroy(qmc_context ctx);
+
+/* Text of the last non-OK status returned on the calling thread ("" if none).  The string
+ * is owned by the library and valid until the next call on this thread. */
+const char* qmc_last_error(void);
+
+/* Library version string, e.g. "qmc-gfx950 1.0". */
+const char* qmc_version(void);
+
+/* ------------------------------------------------------------------ setup ---- */
+
+/* The first `count` primitive polynomials over F_2, ordered by degree and then by their
+ * integer code (bit t = coefficient of x^t), written to host array codes[count].
+ * They define Sobol' dimensions 1.. (Sec. 2.3).  Errors: INVALID_ARGUMENT (codes NULL),
+ * OUT_OF_RANGE (count > 4096). */
+qmc_status qmc_primitive_polynomials(uint32_t count, uint32_t* codes);
+
+/* Sobol' generator matrices for s dimensions (Sec. 2.3, Eq. ts), written to host array
+ * matrices[s][32]: column k (= matrices[j*32+k]) is the image of index bit k, and bit 31
+ * of a column is the coefficient of 2^-1.  Dimension 0 is the identity (van der Corput);
+ * dimension j >= 1 uses the (j-1)-th primitive polynomial of degree d with initial
+ * direction numbers direction_init[j*QMC_MAX_DEGREE + 0 .. d-1] (host; odd, m_k < 2^k)
+ * and the Sobol' recurrence for the rest.
+ * Errors: INVALID_ARGUMENT (NULL, an even or too large m_k), OUT_OF_RANGE (s > QMC_MAX_DIMS
+ * or s == 0, or a polynomial degree above QMC_MAX_DEGREE). */
+qmc_status qmc_sobol_matrices(uint32_t s, const uint32_t* direction_init, uint32_t* matrices);
+
+/* ------------------------------------------------------------- generation ---- */
+
+/* map_u32_to_unifloat (Sec. 2.1, Alg. 1) over an array: out[k] = the largest binary32 not
+ * above in[k] * 2^-32, so every result lies in [0, 1).  in, out: device, n elements each
+ * (may alias exactly).  Errors: INVALID_ARGUMENT (NULL with n > 0). */
+qmc_status qmc_map_u32_to_unifloat(qmc_context ctx, qmc_stream stream,
+                                   const uint32_t* in, float* out, uint64_t n);
+
+/* Points i in [first, first+n) of an s-dimensional digital sequence in base 2 (Eq. ts),
+ * randomised in integers and converted (Sec. 2.1):
+ *     v = C_j a(i)                       generator-matrix product over F_2
+ *     v = NUS(v; nus_seeds[j])           if nus_seeds != NULL (nested uniform scramble)
+ *     v = v + shifts[j] mod 2^32         if shifts != NULL (v ^ shifts[j] with QMC_SHIFT_XOR)
+ *     out_u32[j*ld + (i-first)] = v,  out_f32[j*ld + (i-first)] = map_u32_to_unifloat(v)
+ * NUS(x; s) = brev(P_s(brev(x))) where brev mirrors the 32 bits and P_s is, mod 2^32 with
+ * lo24(v) = v & 0xFFFFFF:  v += s;  v += lo24(v)*0x612362;  v ^= v<<8;
+ * v += lo24(v)*((s>>8)&0xFFFFFE);  v += lo24(v)*0x934C76;  v ^= v<<9;  v ^= v*0xFA8F38AA.
+ * Each output digit is the input digit flipped by a function of the seed and of the more
+ * significant digits only (a nested uniform scramble in the sense of Owen, cited in
+ * Sec. 2.1 and 2.5.2), so digital-net properties are preserved.
+ *   matrices:  device, [s][32] u32 as produced by qmc_sobol_matrices (any matrices allowed).
+ *   nus_seeds, shifts: device [s] u32, or NULL.
+ *   out_u32, out_f32: device, dimension-major with leading dimension ld >= n; either may be
+ *              NULL but not both.  Outputs must not overlap each other or the inputs.
+ *   flags:     0 or QMC_SHIFT_XOR.
+ * Errors: INVALID_ARGUMENT (NULL inputs, both outputs NULL, ld < n, unknown flags),
+ *         OUT_OF_RANGE (s == 0 or s > QMC_MAX_DIMS, first + n > 2^32). n == 0 is a no-op. */
+qmc_status qmc_generate_sobol(qmc_context ctx, qmc_stream stream,
+                              const uint32_t* matrices, uint32_t s,
+                              uint64_t first, uint64_t n,
+                              const uint32_t* nus_seeds, const uint32_t* shifts,
+                              uint32_t flags,
+                              uint32_t* out_u32, float* out_f32, uint64_t ld);
+
+/* Points i in [first, first+n) of the rank-1 lattice sequence (Sec. 2.4, Eq. R1LS) in
+ * base 2 with generator vector g (Alg. 4):
+ *     v = phi_2(i) * g_j mod 1, computed as brev(i) * g_j mod 2^32
+ *         (brev(2^32-1-i) * g_j with QMC_LATTICE_BACKWARD, so the origin comes last)
+ *     v = v + shifts[j] mod 2^32 if shifts != NULL (v ^ shifts[j] with QMC_SHIFT_XOR)
+ *     outputs as for qmc_generate_sobol.
+ *   generator: device [s] u32 (odd components give a Latin hypercube at 2^m points).
+ * Errors as for qmc_generate_sobol; flags may combine QMC_SHIFT_XOR and QMC_LATTICE_BACKWARD. */
+qmc_status qmc_generate_lattice(qmc_context ctx, qmc_stream stream,
+                                const uint32_t* generator, uint32_t s,
+                                uint64_t first, uint64_t n,
+                                const uint32_t* shifts, uint32_t flags,
+                                uint32_t* out_u32, float* out_f32, uint64_t ld);
+
+/* ------------------------------------------------- per-pixel integration ---- */
+/*
+ * Integro-approximation over an image (Sec. 2.5, Sec. 3): pixel p = y * width + x
+ * (row-major) estimates I_p = (1/N_p) sum_{i < N_p} f_p(x_{p,i}) with N_p = counts[p]
+ * samples.  Every pixel owns an independently randomised copy of the sequence (Sec.
+ * 2.5.2), so pixels need no communication and their sample counts may differ.  A call
+ * covers the sample window i in [sample_begin, min(sample_end, N_p)) of every pixel, so
+ * a run can be split into progressive passes whose sums add up exactly.
+ *
+ * Sample i of pixel p, dimension j < d (integers until the last step, Sec. 2.1):
+ *   SOBOL:   v = C_j a(i);  v = NUS(v; seed_pj) with QMC_PIXEL_NUS;
+ *   LATTICE: v = phi_2(i) g_j mod 1 (phi_2(2^32-1-i) with QMC_LATTICE_BACKWARD);
+ *   then v = v + delta_pj mod 2^32 with QMC_PIXEL_SHIFT (v ^ delta_pj with QMC_SHIFT_XOR),
+ *   and x = map_u32_to_unifloat(v).
+ *   seed_pj  = H(H(seed + 2j) ^ p),  delta_pj = H(H(seed + 2j + 1) ^ p), where H is the
+ *   integer hash "pcg" of Jarzynski and Olano (JCGT 2020):
+ *   t = v*747796405 + 2891336453; w = ((t >> ((t >> 28) + 4)) ^ t) * 277803737; H = (w >> 22) ^ w.
+ *   POINTS:  x = table[j * points_ld + offsets[p] + i] (samples materialised beforehand by
+ *   qmc_generate_pixel_samples: the plain generate-then-integrate path).
+ *
+ * Integrands (FP32 on the GPU):
+ *   QMC_F_GENZ (d = 8; pixel_params [P][16]: centres u_0..u_7 then widths a_0..a_7):
+ *     f_p(x) = exp(-sum_{j<4} a_j^2 (x_j - u_j)^2) * cos(2 pi u_4 + sum_{j=4..7} a_j x_j)
+ *   QMC_F_LOBES (shared theta = [centres c (L x d), log-widths l (L x d), weights w (L)]):
+ *     f_p(x) = sum_k w_k exp(-1/2 sum_j ((x_j + delta'_pj - c_kj) e^{-l_kj})^2), with the
+ *     per-pixel offset delta'_pj = fl(fl(0.5 * map_u32_to_unifloat(H(H(pixel_seed + j) ^ p)))
+ *     - 0.25) in [-1/4, 1/4) and x_j + delta'_pj rounded to binary32.
+ */
+#define QMC_SAMPLER_SOBOL 1u
+#define QMC_SAMPLER_LATTICE 2u
+#define QMC_SAMPLER_POINTS 3u
+
+#define QMC_PIXEL_NUS 4u   /* sampler flag: per-pixel nested uniform scramble (SOBOL) */
+#define QMC_PIXEL_SHIFT 8u /* sampler flag: per-pixel rotation (addition, or XOR with QMC_SHIFT_XOR) */
+
+#define QMC_F_GENZ 1u
+#define QMC_F_LOBES 2u
+
+typedef struct {
+    uint32_t kind;           /* QMC_SAMPLER_*                                                     */
+    uint32_t s;              /* dimensions in `table` (>= the integrand's d; <= QMC_MAX_DIMS)      */
+    const void* table;       /* device: SOBOL u32 [s][32] matrices | LATTICE u32 [s] generator |   */
+                             /*         POINTS float32 [s][points_ld] samples                      */
+    uint64_t points_ld;      /* POINTS: leading dimension of table                                 */
+    const uint64_t* offsets; /* POINTS: device [P], slot of sample 0 of pixel p                    */
+    uint32_t seed;           /* per-pixel seeds and rotations are derived from this                */
+    uint32_t flags;          /* QMC_PIXEL_NUS | QMC_PIXEL_SHIFT | QMC_SHIFT_XOR | QMC_LATTICE_BACKWARD */
+} qmc_sampler;
+
+typedef struct {
+    uint32_t kind;             /* QMC_F_GENZ or QMC_F_LOBES                                      */
+    uint32_t d;                /* dimensions consumed: 8 for GENZ; 1..QMC_MAX_DIMS for LOBES     */
+    uint32_t num_lobes;        /* LOBES: L >= 1                                                  */
+    uint32_t pixel_seed;       /* LOBES: seed of the per-pixel offsets                           */
+    const float* params;       /* LOBES: device theta [L*(2d+1)]                                 */
+    const float* pixel_params; /* GENZ: device [P][16]                                           */
+} qmc_integrand;
+
+/* Bytes of device workspace needed by qmc_integrate_pixels (backward = 0) or by
+ * qmc_integrate_pixels_backward (backward = 1) for this problem, in *bytes.  The workspace
+ * holds a work counter and, for the backward pass, per-wavefront gradient partials.
+ * Errors: INVALID_ARGUMENT (NULL), UNSUPPORTED (kind/dimension combination). */
+qmc_status qmc_workspace_size(qmc_context ctx, const qmc_sampler* sampler, const qmc_integrand* integrand,
+                              uint32_t width, uint32_t height, int backward, size_t* bytes);
+
+/* Adds the window sums to sums[p] (if sums != NULL) and writes means[p] = sums[p] / N_p
+ * (or window sum / N_p if sums is NULL; 0 where N_p = 0) if means != NULL.  One persistent
+ * launch covers all pixels whatever their counts; per-pixel sums are reduced in a fixed
+ * order, so results are bitwise reproducible for a given launch configuration.
+ *   counts: device u32 [width*height];  sums, means: device float32 [width*height];
+ *   workspace: device, >= qmc_workspace_size(..., 0) bytes, no initial contents required.
+ * Errors: INVALID_ARGUMENT (NULLs, sums and means both NULL, d > s, bad flags, begin > end),
+ *         UNSUPPORTED (d not supported for the kind), WORKSPACE (too small). */
+qmc_status qmc_integrate_pixels(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
+                                const qmc_integrand* integrand, uint32_t width, uint32_t height,
+                                const uint32_t* counts, uint32_t sample_begin, uint32_t sample_end,
+                                float* sums, float* means, void* workspace, size_t workspace_bytes);
+
+/* Adjoint of qmc_integrate_pixels for QMC_F_LOBES: given grad_means[p] = dL/dI_p, adds
+ *   dL/dtheta = sum_p grad_means[p] / N_p * sum_{i in window} df_p(x_{p,i}) / dtheta
+ * to grad_params[L*(2d+1)] (device float32; the caller zeroes it for a fresh gradient).
+ * Samples are recomputed from (p, i) rather than stored.  Partial gradients are reduced
+ * in FP64 in a fixed order, so the result is bitwise reproducible for a given launch
+ * configuration.  workspace: >= qmc_workspace_size(..., 1) bytes.
+ * Errors as for qmc_integrate_pixels; UNSUPPORTED for integrands other than LOBES. */
+qmc_status qmc_integrate_pixels_backward(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
+                                         const qmc_integrand* integrand, uint32_t width, uint32_t height,
+                                         const uint32_t* counts, uint32_t sample_begin, uint32_t sample_end,
+                                         const float* grad_means, float* grad_params, void* workspace,
+                                         size_t workspace_bytes);
+
+/* Exclusive prefix sums of counts: offsets[p] = sum_{q<p} counts[q] (device u64 [num_pixels+1],
+ * offsets[num_pixels] = total).  workspace: >= 8 * (num_pixels / 1024 + 2) bytes.  Used to lay
+ * out materialised per-pixel samples. */
+qmc_status qmc_sample_offsets(qmc_context ctx, qmc_stream stream, const uint32_t* counts, uint32_t num_pixels,
+                              uint64_t* offsets, void* workspace, size_t workspace_bytes);
+
+/* The plain path's first half: writes sample i < N_p of pixel p, dimension j < d, as
+ * out[j * ld + offsets[p] + i] (float32), exactly the values the fused integration uses
+ * (before any integrand offset).  sampler: SOBOL or LATTICE.  offsets: from
+ * qmc_sample_offsets; ld >= offsets[P]; out: device float32 [d][ld].
+ * workspace: >= 256 bytes of device memory (a work counter). */
+qmc_status qmc_generate_pixel_samples(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler, uint32_t d,
+                                      uint32_t width, uint32_t height, const uint32_t* counts,
+                                      const uint64_t* offsets, float* out, uint64_t ld, void* workspace,
+                                      size_t workspace_bytes);
+
+/* ------------------------------------------- progressive passes (graphs) ---- */
+
+/* Progressive integration (Sec. 2.5: every pixel extends its own sequence, so passes are
+ * added without communication): pass t covers the sample window [t*spp_per_pass,
+ * (t+1)*spp_per_pass) of every pixel (pixels with N_p below the window contribute nothing),
+ * adding into sums; the last pass also writes means (if not NULL).  With use_graph != 0 the
+ * passes are captured once into a hipGraph (on a private stream of the context), cached in
+ * the context under all arguments, and replayed on `stream` with hipGraphLaunch; otherwise
+ * they are enqueued one by one.  The sums after all passes equal one call with the window
+ * [0, passes*spp_per_pass) up to FP32 summation order.
+ *   sums: device float32 [P], required; workspace as for qmc_integrate_pixels.
+ * Errors: as for qmc_integrate_pixels; OUT_OF_RANGE if passes*spp_per_pass >= 2^32;
+ *         DEVICE if capture or instantiation fails. */
+qmc_status qmc_integrate_progressive(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
+                                     const qmc_integrand* integrand, uint32_t width, uint32_t height,
+                                     const uint32_t* counts, uint32_t passes, uint32_t spp_per_pass, float* sums,
+                                     float* means, void* workspace, size_t workspace_bytes, int use_graph);
+
+/* ------------------------------------------------------------- autotuning ---- */
+
+/* Times each launch shape of the materialising kernels (chunks per wavefront 1..32, with and
+ * without non-temporal stores) on `stream` with hipEvents and keeps the fastest in the context
+ * for that sequence kind.  The candidates write the n points of `table` into the caller's
+ * scratch buffers ([s][n] each; either may be NULL but not both).  Synchronises `stream`
+ * (not capturable).  report (may be NULL) receives one JSON line per candidate.
+ * kind: QMC_SAMPLER_SOBOL (table = matrices, nus_seeds/shifts optional) or
+ * QMC_SAMPLER_LATTICE (table = generator, shifts optional). */
+qmc_status qmc_autotune_generate(qmc_context ctx, qmc_stream stream, uint32_t kind, const uint32_t* table,
+                                 uint32_t s, uint64_t n, const uint32_t* nus_seeds, const uint32_t* shifts,
+                                 uint32_t* scratch_u32, float* scratch_f32, char* report, size_t report_bytes);
+
+/* Times the integration launch shapes (persistent grid of 4..32 wavefronts per compute unit,
+ * static or atomic-queue schedule) for this problem and keeps the fastest in the context for
+ * (integrand kind, d, direction).  Forward candidates write means into scratch (device
+ * float32 [P]); backward candidates (backward != 0, grad_means required) add gradients into
+ * scratch (device float32 [n_theta]).  Synchronises `stream`.  report as above. */
+qmc_status qmc_autotune_integrate(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
+                                  const qmc_integrand* integrand, uint32_t width, uint32_t height,
+                                  const uint32_t* counts, uint32_t sample_begin, uint32_t sample_end, int backward,
+                                  const float* grad_means, float* scratch, void* workspace, size_t workspace_bytes,
+                                  char* report, size_t report_bytes);
+
+/* Write / read the context's tuned launch parameters as JSON (host file path). */
+qmc_status qmc_tune_save(qmc_context ctx, const char* path);
+qmc_status qmc_tune_load(qmc_context ctx, const char* path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QMC_H */

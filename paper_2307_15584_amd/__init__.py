@@ -1,0 +1,390 @@
+"""Python binding of libqmc (MI355X / gfx950 quasi-Monte Carlo sampling and integration).
+
+Thin argument marshalling over the C ABI declared in include/qmc.h: every function here
+has the name of the C entry point it calls, takes torch tensors for device buffers and
+passes their pointers and the current torch stream.  All computation happens in the HIP
+kernels of libqmc.so; torch only provides device memory and streams.
+
+u32 data lives in torch.int32 tensors (same bits); use `to_u32(t)` to view it on the host.
+"""
+
+import ctypes
+
+import numpy as np
+
+from ._lib import (  # noqa: F401
+    QMC_F_GENZ,
+    QMC_F_LOBES,
+    QMC_LATTICE_BACKWARD,
+    QMC_MAX_DEGREE,
+    QMC_MAX_DIMS,
+    QMC_PIXEL_NUS,
+    QMC_PIXEL_SHIFT,
+    QMC_SAMPLER_LATTICE,
+    QMC_SAMPLER_POINTS,
+    QMC_SAMPLER_SOBOL,
+    QMC_SHIFT_XOR,
+    Integrand,
+    QMCError,
+    Sampler,
+    check,
+    load,
+)
+
+_contexts = {}
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def context(device=None):
+    """The library context of a CUDA/HIP device (created on first use, kept for the process)."""
+    torch = _torch()
+    if device is None:
+        device = torch.cuda.current_device()
+    if isinstance(device, torch.device):
+        device = device.index if device.index is not None else torch.cuda.current_device()
+    if device not in _contexts:
+        h = ctypes.c_void_p()
+        check(load().qmc_create(int(device), ctypes.byref(h)))
+        _contexts[device] = h
+    return _contexts[device]
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, name, dtype=None):
+    """Device pointer of a contiguous GPU tensor (or None)."""
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a GPU tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype not in dtype:
+        raise TypeError("%s has dtype %s, expected one of %s" % (name, t.dtype, dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _device_of(*ts):
+    for t in ts:
+        if t is not None:
+            return t.device
+    return None
+
+
+def to_u32(t):
+    """Host numpy uint32 view of a tensor holding u32 bit patterns."""
+    return t.detach().cpu().contiguous().numpy().view(np.uint32)
+
+
+def from_u32(a, device="cuda"):
+    """Device int32 tensor holding the bits of a uint32 numpy array."""
+    torch = _torch()
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
+    return torch.from_numpy(a.view(np.int32).copy()).to(device)
+
+
+def _u32_types():
+    torch = _torch()
+    return (torch.int32, torch.uint32) if hasattr(torch, "uint32") else (torch.int32,)
+
+
+# ------------------------------------------------------------------ setup (host) ----
+
+def qmc_primitive_polynomials(count):
+    """The first `count` primitive polynomials over F_2 as uint32 codes (host numpy)."""
+    out = np.zeros(max(count, 1), dtype=np.uint32)
+    check(load().qmc_primitive_polynomials(count, out.ctypes.data_as(ctypes.c_void_p)))
+    return out[:count]
+
+
+def qmc_sobol_matrices(s, direction_init):
+    """Sobol' generator matrices uint32 [s][32] (host numpy) from direction_init [s][16]."""
+    di = np.ascontiguousarray(np.asarray(direction_init, dtype=np.uint32))
+    if di.shape != (s, QMC_MAX_DEGREE):
+        raise ValueError("direction_init must have shape (%d, %d)" % (s, QMC_MAX_DEGREE))
+    out = np.zeros((s, 32), dtype=np.uint32)
+    check(load().qmc_sobol_matrices(s, di.ctypes.data_as(ctypes.c_void_p), out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+# ------------------------------------------------------------- generation (device) ----
+
+def qmc_map_u32_to_unifloat(inp, out=None):
+    """out = map_u32_to_unifloat(inp) elementwise on the GPU; returns out (float32)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(inp.shape, dtype=torch.float32, device=inp.device)
+    pi = _dev_ptr(inp, "inp", _u32_types())
+    po = _dev_ptr(out, "out", (torch.float32,))
+    if out.numel() != inp.numel():
+        raise ValueError("out must have as many elements as inp")
+    check(load().qmc_map_u32_to_unifloat(context(inp.device), _stream(), pi, po, inp.numel()))
+    return out
+
+
+def _check_len(t, s, name):
+    if t is not None and t.numel() < s:
+        raise ValueError("%s needs at least %d entries" % (name, s))
+
+
+def _outputs(s, n, ld, out_u32, out_f32, want_u32, want_f32, device):
+    torch = _torch()
+    ld = n if ld is None else ld
+    if out_u32 is None and want_u32:
+        out_u32 = torch.empty((s, ld), dtype=torch.int32, device=device)
+    if out_f32 is None and want_f32:
+        out_f32 = torch.empty((s, ld), dtype=torch.float32, device=device)
+    for t, name in ((out_u32, "out_u32"), (out_f32, "out_f32")):
+        if t is not None and t.numel() < (s - 1) * ld + n:
+            raise ValueError("%s is too small for s=%d, ld=%d, n=%d" % (name, s, ld, n))
+    return ld, out_u32, out_f32
+
+
+def qmc_generate_sobol(matrices, first, n, nus_seeds=None, shifts=None, flags=0, out_u32=None, out_f32=None,
+                       ld=None, want_u32=True, want_f32=True):
+    """Points i in [first, first+n) of the digital sequence with device matrices [s][32].
+
+    Returns (u32 int32 tensor [s][ld] or None, float32 tensor [s][ld] or None).
+    """
+    torch = _torch()
+    s = matrices.shape[0]
+    if matrices.numel() != s * 32:
+        raise ValueError("matrices must have shape [s][32]")
+    _check_len(nus_seeds, s, "nus_seeds")
+    _check_len(shifts, s, "shifts")
+    ld, out_u32, out_f32 = _outputs(s, n, ld, out_u32, out_f32, want_u32, want_f32, matrices.device)
+    st = load().qmc_generate_sobol(
+        context(matrices.device), _stream(), _dev_ptr(matrices, "matrices", _u32_types()), s, first, n,
+        _dev_ptr(nus_seeds, "nus_seeds", _u32_types()), _dev_ptr(shifts, "shifts", _u32_types()), flags,
+        _dev_ptr(out_u32, "out_u32", _u32_types()), _dev_ptr(out_f32, "out_f32", (torch.float32,)), ld)
+    check(st)
+    return out_u32, out_f32
+
+
+def qmc_generate_lattice(generator, first, n, shifts=None, flags=0, out_u32=None, out_f32=None, ld=None,
+                         want_u32=True, want_f32=True):
+    """Points i in [first, first+n) of the rank-1 lattice sequence with device generator [s]."""
+    torch = _torch()
+    s = generator.shape[0]
+    if generator.dim() != 1:
+        raise ValueError("generator must be a vector [s]")
+    _check_len(shifts, s, "shifts")
+    ld, out_u32, out_f32 = _outputs(s, n, ld, out_u32, out_f32, want_u32, want_f32, generator.device)
+    st = load().qmc_generate_lattice(
+        context(generator.device), _stream(), _dev_ptr(generator, "generator", _u32_types()), s, first, n,
+        _dev_ptr(shifts, "shifts", _u32_types()), flags,
+        _dev_ptr(out_u32, "out_u32", _u32_types()), _dev_ptr(out_f32, "out_f32", (torch.float32,)), ld)
+    check(st)
+    return out_u32, out_f32
+
+
+# -------------------------------------------------------- per-pixel integration ----
+
+class PixelSampler:
+    """A qmc_sampler plus the device tensors it points to (kept alive with it)."""
+
+    def __init__(self, kind, table, seed=0, flags=0, points_ld=0, offsets=None, s=None):
+        self.table = table
+        self.offsets = offsets
+        self.kind = kind
+        self.seed = seed
+        self.flags = flags
+        if s is None:
+            s = table.shape[0]
+        self.s = s
+        self.c = Sampler(kind, s, _dev_ptr(table, "table").value, points_ld,
+                         _dev_ptr(offsets, "offsets").value if offsets is not None else None, seed & 0xFFFFFFFF,
+                         flags)
+
+    @classmethod
+    def sobol(cls, matrices, seed, flags=QMC_PIXEL_NUS | QMC_PIXEL_SHIFT):
+        if matrices.numel() != matrices.shape[0] * 32:
+            raise ValueError("matrices must have shape [s][32]")
+        return cls(QMC_SAMPLER_SOBOL, matrices, seed, flags)
+
+    @classmethod
+    def lattice(cls, generator, seed, flags=QMC_PIXEL_SHIFT):
+        return cls(QMC_SAMPLER_LATTICE, generator, seed, flags)
+
+    @classmethod
+    def points(cls, samples, offsets):
+        """Materialised samples [d][ld] float32 with per-pixel offsets (int64 [P+1])."""
+        return cls(QMC_SAMPLER_POINTS, samples, 0, 0, points_ld=samples.shape[1], offsets=offsets,
+                   s=samples.shape[0])
+
+
+class PixelIntegrand:
+    """A qmc_integrand plus its device tensors."""
+
+    def __init__(self, kind, d, params=None, pixel_params=None, num_lobes=0, pixel_seed=0):
+        self.params = params
+        self.pixel_params = pixel_params
+        self.kind, self.d, self.num_lobes, self.pixel_seed = kind, d, num_lobes, pixel_seed
+        torch = _torch()
+        self.c = Integrand(kind, d, num_lobes, pixel_seed & 0xFFFFFFFF,
+                           _dev_ptr(params, "params", (torch.float32,)).value if params is not None else None,
+                           _dev_ptr(pixel_params, "pixel_params", (torch.float32,)).value
+                           if pixel_params is not None else None)
+
+    @classmethod
+    def genz(cls, pixel_params):
+        return cls(QMC_F_GENZ, 8, pixel_params=pixel_params)
+
+    @classmethod
+    def lobes(cls, params, num_lobes, d, pixel_seed):
+        if params.numel() != num_lobes * (2 * d + 1):
+            raise ValueError("params must have L*(2d+1) entries")
+        return cls(QMC_F_LOBES, d, params=params, num_lobes=num_lobes, pixel_seed=pixel_seed)
+
+    def with_params(self, params):
+        return PixelIntegrand(self.kind, self.d, params, self.pixel_params, self.num_lobes, self.pixel_seed)
+
+
+def qmc_workspace_size(sampler, integrand, width, height, backward=False):
+    n = ctypes.c_size_t()
+    check(load().qmc_workspace_size(context(), ctypes.byref(sampler.c), ctypes.byref(integrand.c), width, height,
+                                    1 if backward else 0, ctypes.byref(n)))
+    return n.value
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _check_counts(counts, P):
+    if counts.numel() != P:
+        raise ValueError("counts must have width*height entries")
+
+
+def qmc_integrate_pixels(sampler, integrand, width, height, counts, sample_begin=0, sample_end=0xFFFFFFFF,
+                         sums=None, means=None, workspace=None):
+    """Per-pixel estimates; returns means (allocated when neither sums nor means is given)."""
+    torch = _torch()
+    P = width * height
+    _check_counts(counts, P)
+    if sums is None and means is None:
+        means = torch.empty(P, dtype=torch.float32, device=counts.device)
+    for t, nm in ((sums, "sums"), (means, "means")):
+        if t is not None and t.numel() != P:
+            raise ValueError("%s must have width*height entries" % nm)
+    if workspace is None:
+        workspace = _workspace(qmc_workspace_size(sampler, integrand, width, height, False), counts.device)
+    check(load().qmc_integrate_pixels(
+        context(counts.device), _stream(), ctypes.byref(sampler.c), ctypes.byref(integrand.c), width, height,
+        _dev_ptr(counts, "counts", _u32_types()), sample_begin, sample_end,
+        _dev_ptr(sums, "sums", (torch.float32,)), _dev_ptr(means, "means", (torch.float32,)),
+        _dev_ptr(workspace, "workspace"), workspace.numel()))
+    return means if means is not None else sums
+
+
+def qmc_integrate_pixels_backward(sampler, integrand, width, height, counts, grad_means, grad_params=None,
+                                  sample_begin=0, sample_end=0xFFFFFFFF, workspace=None):
+    """Adds dL/dtheta into grad_params (zeros if not given); returns grad_params."""
+    torch = _torch()
+    P = width * height
+    _check_counts(counts, P)
+    if grad_means.numel() != P:
+        raise ValueError("grad_means must have width*height entries")
+    if grad_params is None:
+        grad_params = torch.zeros(integrand.params.numel(), dtype=torch.float32, device=counts.device)
+    if workspace is None:
+        workspace = _workspace(qmc_workspace_size(sampler, integrand, width, height, True), counts.device)
+    check(load().qmc_integrate_pixels_backward(
+        context(counts.device), _stream(), ctypes.byref(sampler.c), ctypes.byref(integrand.c), width, height,
+        _dev_ptr(counts, "counts", _u32_types()), sample_begin, sample_end,
+        _dev_ptr(grad_means, "grad_means", (torch.float32,)), _dev_ptr(grad_params, "grad_params", (torch.float32,)),
+        _dev_ptr(workspace, "workspace"), workspace.numel()))
+    return grad_params
+
+
+def qmc_sample_offsets(counts):
+    """int64 [P+1] exclusive prefix sums of counts (computed on the GPU)."""
+    torch = _torch()
+    P = counts.numel()
+    offsets = torch.empty(P + 1, dtype=torch.int64, device=counts.device)
+    ws = _workspace(8 * (P // 1024 + 2), counts.device)
+    check(load().qmc_sample_offsets(context(counts.device), _stream(), _dev_ptr(counts, "counts", _u32_types()), P,
+                                    _dev_ptr(offsets, "offsets"), _dev_ptr(ws, "workspace"), ws.numel()))
+    return offsets
+
+
+def qmc_generate_pixel_samples(sampler, d, width, height, counts, offsets, total, out=None):
+    """Materialised samples float32 [d][total] (the plain path's generation step)."""
+    torch = _torch()
+    _check_counts(counts, width * height)
+    if out is None:
+        out = torch.empty((d, max(int(total), 1)), dtype=torch.float32, device=counts.device)
+    ws = _workspace(256, counts.device)
+    check(load().qmc_generate_pixel_samples(
+        context(counts.device), _stream(), ctypes.byref(sampler.c), d, width, height,
+        _dev_ptr(counts, "counts", _u32_types()), _dev_ptr(offsets, "offsets"), _dev_ptr(out, "out"),
+        out.shape[1], _dev_ptr(ws, "workspace"), ws.numel()))
+    return out
+
+
+def qmc_integrate_progressive(sampler, integrand, width, height, counts, passes, spp_per_pass, sums, means=None,
+                              workspace=None, use_graph=True):
+    """passes x spp_per_pass windows added into sums (graph-captured and replayed when use_graph)."""
+    torch = _torch()
+    P = width * height
+    _check_counts(counts, P)
+    if workspace is None:
+        workspace = _workspace(qmc_workspace_size(sampler, integrand, width, height, False), counts.device)
+    check(load().qmc_integrate_progressive(
+        context(counts.device), _stream(), ctypes.byref(sampler.c), ctypes.byref(integrand.c), width, height,
+        _dev_ptr(counts, "counts", _u32_types()), passes, spp_per_pass, _dev_ptr(sums, "sums", (torch.float32,)),
+        _dev_ptr(means, "means", (torch.float32,)), _dev_ptr(workspace, "workspace"), workspace.numel(),
+        1 if use_graph else 0))
+    return sums
+
+
+def qmc_autotune_generate(kind, table, n, nus_seeds=None, shifts=None, scratch_u32=None, scratch_f32=None):
+    """Tunes the materialising kernels of one sequence kind; returns the per-candidate report."""
+    torch = _torch()
+    s = table.shape[0]
+    if scratch_u32 is None and scratch_f32 is None:
+        scratch_u32 = torch.empty((s, n), dtype=torch.int32, device=table.device)
+        scratch_f32 = torch.empty((s, n), dtype=torch.float32, device=table.device)
+    rep = ctypes.create_string_buffer(8192)
+    check(load().qmc_autotune_generate(
+        context(table.device), _stream(), kind, _dev_ptr(table, "table"), s, n, _dev_ptr(nus_seeds, "nus_seeds"),
+        _dev_ptr(shifts, "shifts"), _dev_ptr(scratch_u32, "scratch_u32"), _dev_ptr(scratch_f32, "scratch_f32"),
+        rep, len(rep)))
+    return rep.value.decode()
+
+
+def qmc_autotune_integrate(sampler, integrand, width, height, counts, sample_begin=0, sample_end=0xFFFFFFFF,
+                           backward=False, grad_means=None):
+    """Tunes the integration launch shape for this problem; returns the per-candidate report."""
+    torch = _torch()
+    P = width * height
+    n = integrand.params.numel() if backward else P
+    scratch = torch.zeros(n, dtype=torch.float32, device=counts.device)
+    ws = _workspace(qmc_workspace_size(sampler, integrand, width, height, backward), counts.device)
+    rep = ctypes.create_string_buffer(8192)
+    check(load().qmc_autotune_integrate(
+        context(counts.device), _stream(), ctypes.byref(sampler.c), ctypes.byref(integrand.c), width, height,
+        _dev_ptr(counts, "counts", _u32_types()), sample_begin, sample_end, 1 if backward else 0,
+        _dev_ptr(grad_means, "grad_means"), _dev_ptr(scratch, "scratch"), _dev_ptr(ws, "workspace"), ws.numel(),
+        rep, len(rep)))
+    return rep.value.decode()
+
+
+def qmc_tune_save(path):
+    check(load().qmc_tune_save(context(), path.encode()))
+
+
+def qmc_tune_load(path):
+    check(load().qmc_tune_load(context(), path.encode()))
+
+
+from .autograd import QMCIntegrate, integrate  # noqa: E402,F401

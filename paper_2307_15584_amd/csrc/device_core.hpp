@@ -1,0 +1,59 @@
+// Device-side integer core shared by all kernels: float conversion (Sec. 2.1, Alg. 1),
+// the nested uniform scramble and shifts (Sec. 2.1, 2.3), lattice points (Sec. 2.4) and
+// the per-pixel hash.  Everything stays in 32-bit integers until the final conversion.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace qmc {
+namespace dev {
+
+__device__ __forceinline__ uint32_t brev(uint32_t x) { return __builtin_bitreverse32(x); }
+
+// Largest binary32 not above u * 2^-32 (never 1).  z leading zeros put the leading one of
+// u at bit 31 of (u << z); its top 24 bits (exactly representable) times 2^(-z-24) is the
+// truncated value.  u = 0 is computed as if u = 1 for the shift count and yields 0.
+__device__ __forceinline__ float u32_to_unifloat(uint32_t u) {
+    const uint32_t z = __builtin_clz(u | 1u);
+    const uint32_t m = (u << z) >> 8;
+    return __builtin_ldexpf(static_cast<float>(m), -static_cast<int>(z) - 24);
+}
+
+// The low-to-high mixing P_s of the nested uniform scramble, applied to the mirrored value.
+// sm = (s >> 8) & 0xFFFFFE is the seed-dependent even multiplier, precomputed per seed.
+// __umul24 multiplies the low 24 bits of both operands (every multiplier is below 2^24).
+__device__ __forceinline__ uint32_t nus_permute(uint32_t v, uint32_t s, uint32_t sm) {
+    v += s;
+    v = __umul24(v, 0x612362u) + v;
+    v ^= v << 8;
+    v = __umul24(v, sm) + v;
+    v = __umul24(v, 0x934C76u) + v;
+    v ^= v << 9;
+    v ^= v * 0xFA8F38AAu;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t seed_multiplier(uint32_t s) { return (s >> 8) & 0xFFFFFEu; }
+
+// Nested uniform scramble of a value already given in mirrored (bit-reversed) form.
+__device__ __forceinline__ uint32_t nus_from_mirrored(uint32_t vr, uint32_t s, uint32_t sm) {
+    return brev(nus_permute(vr, s, sm));
+}
+
+template <bool XOR>
+__device__ __forceinline__ uint32_t apply_shift(uint32_t v, uint32_t d) {
+    return XOR ? (v ^ d) : (v + d);
+}
+
+// Integer hash "pcg" (Jarzynski and Olano, JCGT 2020): a PCG state step followed by the
+// RXS-M-XS output permutation.
+__device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
+    const uint32_t state = v * 747796405u + 2891336453u;
+    const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
+}  // namespace dev
+}  // namespace qmc

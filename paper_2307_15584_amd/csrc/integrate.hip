@@ -1,0 +1,1047 @@
+// Per-pixel QMC integro-approximation (Sec. 2.5): every pixel integrates with its own
+// randomised copy of a low-discrepancy sequence (Sec. 2.5.2), so pixels are independent and
+// only a final per-pixel reduction is needed; counts may differ from pixel to pixel.
+//
+// Work decomposition (one persistent launch, any mix of counts):
+//   * a task is a tile of kTile = 64 consecutive pixels; wavefronts take tasks from a
+//     static interleave or from an atomic queue (chosen per problem by the autotuner);
+//   * lane q of the wavefront reads the count of pixel q of the tile;
+//   * pixels with at least 64 samples in the window ("big") are processed one at a time by
+//     the whole wavefront: their per-dimension seeds are computed by lanes j < d once and
+//     shared through LDS, and lane l takes samples l, l+64, ...;
+//   * the remaining pixels are packed: their samples are laid end to end and processed 64
+//     per round, one per lane;
+//   * sample index i = begin + k of dimension j is C_j (begin + k); with begin a multiple of
+//     64 it splits into a per-round part (advanced by one XOR per round, like the
+//     materialising kernels) and a per-lane part C_j k, k < 64, from an LDS table.
+// Consumers of the samples:
+//   * Genz (per-pixel parameters): one sample per lane; big pixels accumulate per lane and
+//     finish with one butterfly reduction, packed pixels with a segmented scan per round;
+//   * Gaussian lobes (parameters shared by all pixels), forward and adjoint: each round of
+//     samples is staged in LDS and every lane owns one lobe (for d > 32, half of a lobe's
+//     dimensions, so 32 lobes still fill a wavefront): t_j = fma(y_j, st_j, b_j) with
+//     st = sqrt(log2(e)/2) e^-l and b = -c st, E = sum t_j^2, G = exp2(-E).  The forward pass
+//     reduces across lanes once per pixel; the adjoint needs no cross-lane reduction at all
+//     and writes one partial gradient per task, which two further kernels sum in FP64 in
+//     task order.
+// Results never depend on which wavefront ran which task, so they are bitwise reproducible.
+#include <cmath>
+
+#include "common.hpp"
+#include "device_core.hpp"
+
+namespace qmc {
+
+IntegrateTune& integrate_tune(qmc_context ctx, uint32_t fkind, uint32_t d, bool backward);
+
+namespace {
+
+constexpr uint32_t kWave = 64;
+constexpr uint32_t kTile = 64;   // pixels per task
+constexpr uint32_t kQI = 26;     // stride entries for index bits 6..31
+constexpr uint32_t kBlock = 256;
+constexpr uint32_t kWavesPerBlock = kBlock / kWave;
+constexpr float kKappa = 0.84932180028801904f;  // sqrt(log2(e) / 2): exp(-r^2/2) = exp2(-(kKappa r)^2)
+constexpr uint32_t kChunkTasks = 256;           // tasks per first-level reduction block
+
+struct Args {
+    // sampler
+    uint32_t skind, s, seed, sflags;
+    uint32_t sxor;  // shift by XOR instead of addition
+    const uint32_t* table;
+    const float* points;
+    uint64_t points_ld;
+    const uint64_t* offsets;
+    // integrand
+    uint32_t fkind, d, L, pixel_seed;
+    const float* params;        // theta (lobes)
+    const float* pixel_params;  // Genz [P][16]
+    // problem
+    uint32_t num_pixels;
+    const uint32_t* counts;
+    uint32_t begin, end;
+    uint32_t aligned;  // begin % 64 == 0
+    float* sums;
+    float* means;
+    const float* grad_means;
+    // materialised samples (plain path)
+    float* out;
+    uint64_t out_ld;
+    // schedule
+    uint32_t num_tasks;
+    uint32_t* queue;
+    uint32_t dynamic;
+    uint32_t total_waves;
+    // adjoint
+    float* partials;  // [num_tasks][n_theta]
+    uint32_t n_theta;
+};
+
+// -------------------------------------------------------------- wave helpers ----
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Orders this wavefront's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total) {
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, kWave);
+        if (lane_id() >= static_cast<uint32_t>(o)) x += y;
+    }
+    *total = __shfl(x, 63, kWave);
+    return x - v;
+}
+
+// Inclusive scan of v over runs of equal `key` (runs are contiguous in lane order).
+__device__ __forceinline__ float segmented_scan(float v, uint32_t key) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const float y = __shfl_up(v, o, kWave);
+        const uint32_t ky = __shfl_up(key, o, kWave);
+        if (lane_id() >= static_cast<uint32_t>(o) && ky == key) v += y;
+    }
+    return v;
+}
+
+// Owner of packed slot g: the largest lane q with off_q <= g (offsets are non-decreasing, so
+// this is the pixel holding the slot; six fixed steps keep every lane active for the shuffles).
+__device__ __forceinline__ uint32_t packed_owner(uint32_t off, uint32_t g) {
+    uint32_t q = 0;
+#pragma unroll
+    for (int b = 5; b >= 0; --b) {
+        const uint32_t cand = q | (1u << b);
+        if (__shfl(off, cand, kWave) <= g) q = cand;
+    }
+    return q;
+}
+
+__device__ __forceinline__ uint32_t next_task(const Args& a, uint32_t wave_global, uint32_t iter) {
+    if (a.dynamic) {
+        uint32_t t = 0;
+        if (lane_id() == 0) t = atomicAdd(a.queue, 1u);
+        return __shfl(t, 0, kWave);
+    }
+    return wave_global + iter * a.total_waves;
+}
+
+// ------------------------------------------------------------- sampler state ----
+
+template <int D>
+struct SamplerLds {
+    uint32_t T[D][kWave];  // C_j k for k < 64 (mirrored when scrambling)
+    uint32_t Q[D][kQI];    // XOR of columns 6..6+t (mirrored when scrambling)
+    uint32_t B0[D];        // C_j begin
+    uint32_t kn[D], kc[D], kd[D];
+    uint32_t g[D];
+};
+
+// Per-wave values of the big pixel being processed.
+template <int D>
+struct PixelLds {
+    uint32_t seed[D], sm[D], shift[D];
+    float delta[D];
+    uint32_t B[D];  // current per-round index part
+};
+
+__device__ __forceinline__ float pixel_delta(uint32_t kd, uint32_t p) {
+    const float u = dev::u32_to_unifloat(dev::pcg_hash(kd ^ p));
+    return __fsub_rn(__fmul_rn(0.5f, u), 0.25f);
+}
+
+template <int D, uint32_t SK, bool NUS>
+__device__ void stage_sampler(SamplerLds<D>& S, const Args& a) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t d = min(a.d, static_cast<uint32_t>(D));
+    if constexpr (SK == QMC_SAMPLER_SOBOL) {
+        for (uint32_t e = tid; e < d * kWave; e += blockDim.x) {
+            const uint32_t j = e / kWave, k = e % kWave;
+            uint32_t x = 0;
+            for (uint32_t b = 0; b < 6; ++b)
+                if ((k >> b) & 1u) x ^= a.table[j * 32 + b];
+            S.T[j][k] = NUS ? dev::brev(x) : x;
+        }
+        for (uint32_t e = tid; e < d * kQI; e += blockDim.x) {
+            const uint32_t j = e / kQI, t = e % kQI;
+            uint32_t x = 0;
+            for (uint32_t b = 0; b <= t; ++b) x ^= a.table[j * 32 + 6 + b];
+            S.Q[j][t] = NUS ? dev::brev(x) : x;
+        }
+        for (uint32_t j = tid; j < d; j += blockDim.x) {
+            uint32_t x = 0;
+            for (uint32_t b = 0; b < 32; ++b)
+                if ((a.begin >> b) & 1u) x ^= a.table[j * 32 + b];
+            S.B0[j] = NUS ? dev::brev(x) : x;
+        }
+    }
+    for (uint32_t j = tid; j < d; j += blockDim.x) {
+        S.kn[j] = dev::pcg_hash(a.seed + 2u * j);
+        S.kc[j] = dev::pcg_hash(a.seed + 2u * j + 1u);
+        S.kd[j] = dev::pcg_hash(a.pixel_seed + j);
+        if constexpr (SK == QMC_SAMPLER_LATTICE) S.g[j] = a.table[j];
+    }
+}
+
+// Per-dimension index part of sample i for the Sobol' sampler.  Aligned windows use the
+// per-round base (lane part from the LDS table at k); otherwise the plain matrix product
+// C_j i is formed here, looping over index bits outside and dimensions inside so that the
+// per-dimension values stay in registers.
+template <int D, uint32_t SK, bool NUS>
+__device__ __forceinline__ void index_part(uint32_t (&v)[D], const SamplerLds<D>& S, const Args& a, uint32_t i,
+                                           uint32_t k, const uint32_t (&base)[D], bool use_base) {
+    if constexpr (SK == QMC_SAMPLER_SOBOL) {
+        if (use_base) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) v[j] = base[j] ^ S.T[j][k];
+        } else {
+#pragma unroll
+            for (int j = 0; j < D; ++j) v[j] = 0u;
+            for (uint32_t b = 0; b < 32; ++b) {
+                if ((i >> b) & 1u) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j)
+                        if (uint32_t(j) < a.d) v[j] ^= a.table[j * 32 + b];
+                }
+            }
+            if constexpr (NUS) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) v[j] = dev::brev(v[j]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = 0u;
+    }
+}
+
+// Components j < d of sample i of pixel p into x (x[j] = 0 for j >= d).
+//   k:      i - begin, the per-lane table index when use_base (k < 64);
+//   base:   per-round index part, used when use_base (else C_j i is formed directly -- any begin);
+//   PX:     per-pixel values of a big pixel (NULL: derive them from the hash per lane);
+//   valid:  false for lanes past the end of a window, which must not read materialised samples.
+template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK>
+__device__ __forceinline__ void sample_point(float (&x)[D], const SamplerLds<D>& S, const PixelLds<D>* PX,
+                                             const Args& a, uint32_t p, uint32_t i, uint32_t k,
+                                             const uint32_t (&base)[D], bool use_base, bool valid) {
+    if constexpr (SK == QMC_SAMPLER_POINTS) {
+        const uint64_t off = valid ? a.offsets[p] + i : 0;
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            x[j] = (valid && uint32_t(j) < a.d) ? a.points[uint64_t(j) * a.points_ld + off] : 0.0f;
+    } else {
+        uint32_t ip[D];
+        index_part<D, SK, NUS>(ip, S, a, i, k, base, use_base);
+        const uint32_t bi = (SK == QMC_SAMPLER_LATTICE) ? dev::brev(BACK ? ~i : i) : 0u;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            x[j] = 0.0f;
+            if (uint32_t(j) < a.d) {
+                uint32_t v = (SK == QMC_SAMPLER_SOBOL) ? ip[j] : bi * S.g[j];
+                if constexpr (NUS) {
+                    uint32_t sd, sm;
+                    if (PX) {
+                        sd = PX->seed[j];
+                        sm = PX->sm[j];
+                    } else {
+                        sd = dev::pcg_hash(S.kn[j] ^ p);
+                        sm = dev::seed_multiplier(sd);
+                    }
+                    v = dev::nus_from_mirrored(v, sd, sm);
+                }
+                if constexpr (SHIFT) {
+                    const uint32_t sh = PX ? PX->shift[j] : dev::pcg_hash(S.kc[j] ^ p);
+                    v = a.sxor ? (v ^ sh) : (v + sh);
+                }
+                x[j] = dev::u32_to_unifloat(v);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------- tile walker ----
+//
+// Visits every sample of the tile's window in rounds of at most 64 (one per lane; the valid
+// lanes of a round are the prefix lane < count).  Calls, in order:
+//   on_big_begin(q)                                 before the rounds of big pixel q;
+//   on_round(x, count, q, p, is_big, slot0, i)      for each round (x: this lane's sample,
+//                                                   q/p: its pixel in the tile / image,
+//                                                   slot0: packed slot of lane 0, i: its index);
+//   on_big_end(q)                                   after the rounds of big pixel q.
+// Packed pixels follow the big ones, in pixel order.  With DELTA the per-pixel integrand
+// offsets are added (y = x + delta, rounded to binary32).
+template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK, bool DELTA, typename BigBegin, typename Round,
+          typename BigEnd>
+__device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S, PixelLds<D>& PX, uint32_t task,
+                                          uint32_t n, bool inb, uint32_t off, uint32_t total_small,
+                                          BigBegin&& on_big_begin, Round&& on_round, BigEnd&& on_big_end) {
+    const uint32_t lane = lane_id();
+    const uint32_t p0 = task * kTile;
+    uint64_t bigmask = __ballot(inb && n >= kWave);
+    while (bigmask) {
+        const uint32_t q = __builtin_ctzll(bigmask);
+        bigmask &= bigmask - 1;
+        const uint32_t pp = p0 + q;
+        const uint32_t nn = __shfl(n, q, kWave);
+        if (lane < D && lane < a.d) {
+            if constexpr (NUS) {
+                const uint32_t sd = dev::pcg_hash(S.kn[lane] ^ pp);
+                PX.seed[lane] = sd;
+                PX.sm[lane] = dev::seed_multiplier(sd);
+            }
+            if constexpr (SHIFT) PX.shift[lane] = dev::pcg_hash(S.kc[lane] ^ pp);
+            if constexpr (DELTA) PX.delta[lane] = pixel_delta(S.kd[lane], pp);
+            if constexpr (SK == QMC_SAMPLER_SOBOL) PX.B[lane] = S.B0[lane];
+        }
+        wave_sync();
+        on_big_begin(q);
+        const uint32_t rounds = (nn + kWave - 1) / kWave;
+        for (uint32_t r = 0; r < rounds; ++r) {
+            const uint32_t k = r * kWave + lane;
+            const uint32_t count = min(nn - r * kWave, kWave);
+            float x[D];
+            uint32_t base[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                base[j] = (SK == QMC_SAMPLER_SOBOL && a.aligned && uint32_t(j) < a.d) ? PX.B[j] : 0u;
+            sample_point<D, SK, NUS, SHIFT, BACK>(x, S, &PX, a, pp, a.begin + k, lane, base, a.aligned != 0,
+                                                  lane < count);
+            if constexpr (DELTA) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) x[j] = uint32_t(j) < a.d ? x[j] + PX.delta[j] : 0.0f;
+            }
+            on_round(x, count, q, pp, true, 0u, a.begin + k);
+            if constexpr (SK == QMC_SAMPLER_SOBOL) {
+                if (a.aligned && r + 1 < rounds) {
+                    const uint32_t h = (a.begin >> 6) + r;
+                    const uint32_t t = min(static_cast<uint32_t>(__builtin_ctz(h + 1u)), kQI - 1);
+                    wave_sync();
+                    if (lane < D && lane < a.d) PX.B[lane] ^= S.Q[lane][t];
+                    wave_sync();
+                }
+            }
+        }
+        on_big_end(q);
+        wave_sync();
+    }
+
+    for (uint32_t slot0 = 0; slot0 < total_small; slot0 += kWave) {
+        const uint32_t g = slot0 + lane;
+        const uint32_t count = min(total_small - slot0, kWave);
+        const bool valid = lane < count;
+        const uint32_t qo = packed_owner(off, g);
+        const uint32_t offq = __shfl(off, qo, kWave);
+        const uint32_t q = valid ? qo : 0u;
+        const uint32_t pp = p0 + q;
+        const uint32_t k = valid ? g - offq : 0u;
+        float x[D];
+        uint32_t base[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) base[j] = (SK == QMC_SAMPLER_SOBOL && a.aligned && uint32_t(j) < a.d) ? S.B0[j] : 0u;
+        sample_point<D, SK, NUS, SHIFT, BACK>(x, S, nullptr, a, pp, a.begin + k, k & (kWave - 1), base,
+                                              a.aligned != 0, valid);
+        if constexpr (DELTA) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) x[j] = uint32_t(j) < a.d ? x[j] + pixel_delta(S.kd[j], pp) : 0.0f;
+        }
+        on_round(x, count, q, pp, false, slot0, a.begin + k);
+    }
+}
+
+// Per-tile bookkeeping common to every consumer: window counts and packed offsets.
+struct TileInfo {
+    uint32_t p;      // this lane's pixel
+    bool inb;        // p < num_pixels
+    uint32_t n;      // samples of p in the window
+    uint32_t ns;     // n if p is packed, else 0
+    uint32_t off;    // packed slot of p's first sample
+    uint32_t total;  // packed slots in the tile
+};
+
+__device__ __forceinline__ TileInfo tile_info(const Args& a, uint32_t task) {
+    TileInfo t;
+    t.p = task * kTile + lane_id();
+    t.inb = t.p < a.num_pixels;
+    const uint32_t N = t.inb ? a.counts[t.p] : 0u;
+    const uint32_t hi = min(N, a.end);
+    t.n = hi > a.begin ? hi - a.begin : 0u;
+    t.ns = (t.inb && t.n < kWave) ? t.n : 0u;
+    t.off = wave_excl_scan(t.ns, &t.total);
+    return t;
+}
+
+__device__ __forceinline__ void write_pixel(const Args& a, uint32_t p, float window_sum) {
+    const uint32_t N = a.counts[p];
+    float total = window_sum;
+    if (a.sums) {
+        total = a.sums[p] + window_sum;
+        a.sums[p] = total;
+    }
+    if (a.means) a.means[p] = N ? total / static_cast<float>(N) : 0.0f;
+}
+
+// Runs body(task) for every task this wavefront obtains.
+template <typename F>
+__device__ __forceinline__ void for_each_task(const Args& a, F&& body) {
+    const uint32_t wave_global = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    for (uint32_t it = 0;; ++it) {
+        const uint32_t task = next_task(a, wave_global, it);
+        if (task >= a.num_tasks) break;
+        body(task);
+    }
+}
+
+// ------------------------------------------------------------ Genz forward ----
+
+// Genz product: exp(-sum_{j<4} a_j^2 (x_j - u_j)^2) * cos(2 pi u_4 + sum_{j>=4} a_j x_j).
+__device__ __forceinline__ float genz_eval(const Args& a, uint32_t p, const float (&x)[8]) {
+    const float* pp = a.pixel_params + uint64_t(p) * 16;
+    float e = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float t = pp[8 + j] * (x[j] - pp[j]);
+        e = fmaf(t, t, e);
+    }
+    float ph = 6.28318530717958648f * pp[4];
+#pragma unroll
+    for (int j = 4; j < 8; ++j) ph = fmaf(pp[8 + j], x[j], ph);
+    return expf(-e) * cosf(ph);
+}
+
+template <uint32_t SK, bool NUS, bool SHIFT, bool BACK>
+__global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
+    constexpr int D = 8;
+    __shared__ SamplerLds<D> S;
+    __shared__ PixelLds<D> PXs[kWavesPerBlock];
+    stage_sampler<D, SK, NUS>(S, a);
+    __syncthreads();
+    PixelLds<D>& PX = PXs[threadIdx.x >> 6];
+    const uint32_t lane = lane_id();
+    for_each_task(a, [&](uint32_t task) {
+        const TileInfo ti = tile_info(a, task);
+        float big_acc = 0.0f, small_acc = 0.0f;
+        walk_tile<D, SK, NUS, SHIFT, BACK, false>(
+            a, S, PX, task, ti.n, ti.inb, ti.off, ti.total, [&](uint32_t) { big_acc = 0.0f; },
+            [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t pp, bool is_big, uint32_t slot0, uint32_t) {
+                float f = genz_eval(a, pp, x);
+                if (lane >= count) f = 0.0f;
+                if (is_big) {
+                    big_acc += f;
+                } else {
+                    // Sum each pixel's run within the round; the owner lane pulls the run's end.
+                    const float sc = segmented_scan(f, lane < count ? q : 0xFFFFFFFFu);
+                    const bool has = ti.ns > 0 && ti.off < slot0 + kWave && ti.off + ti.ns > slot0;
+                    const uint32_t e = has ? min(ti.off + ti.ns, slot0 + kWave) - 1 - slot0 : 0u;
+                    const float part = __shfl(sc, e, kWave);
+                    if (has) small_acc += part;
+                }
+            },
+            [&](uint32_t q) {
+                const float t = wave_sum(big_acc);
+                if (lane == 0) write_pixel(a, task * kTile + q, t);
+            });
+        if (ti.inb && ti.n < kWave) write_pixel(a, ti.p, small_acc);
+    });
+}
+
+// ----------------------------------------------------- lobes: shared layout ----
+
+// Lane -> (half h, lobe slot).  DH dimensions per lane, H = D / DH halves, LPG lobes per group.
+template <int D>
+struct LobeLayout {
+    static constexpr int DH = D > 32 ? 32 : D;
+    static constexpr int H = D / DH;
+    static constexpr uint32_t LPG = kWave / H;
+};
+
+template <int D>
+struct StageLds {
+    float y[kWave][D + 1];
+    float scale[kWave];  // adjoint weight of the sample (gI_p / N_p)
+    uint32_t q[kWave];   // tile-local pixel of the sample
+};
+
+// Loads this lane's lobe parameters for group kg: st = kKappa e^-l, b = -c st (zero when the
+// lane owns no lobe or the dimension is unused, so those terms vanish).
+template <int D>
+__device__ __forceinline__ void load_lobe(const Args& a, uint32_t kg, float (&st)[LobeLayout<D>::DH],
+                                          float (&b)[LobeLayout<D>::DH], float* w, uint32_t* lobe, bool* own) {
+    using LL = LobeLayout<D>;
+    const uint32_t lane = lane_id();
+    const uint32_t h = lane / LL::LPG;
+    const uint32_t k = kg * LL::LPG + lane % LL::LPG;
+    *lobe = k;
+    *own = k < a.L;
+    const uint32_t d = a.d, L = a.L;
+#pragma unroll
+    for (int jj = 0; jj < LL::DH; ++jj) {
+        const uint32_t j = h * LL::DH + jj;
+        if (*own && j < d) {
+            const float c = a.params[k * d + j];
+            const float l = a.params[L * d + k * d + j];
+            st[jj] = kKappa * expf(-l);
+            b[jj] = -c * st[jj];
+        } else {
+            st[jj] = 0.0f;
+            b[jj] = 0.0f;
+        }
+    }
+    *w = *own ? a.params[2 * L * d + k] : 0.0f;
+}
+
+// E = sum_j t_j^2 over all d dimensions of this lane's lobe for staged sample m; t receives
+// this lane's half of the t_j.
+template <int D>
+__device__ __forceinline__ float lobe_exponent(const StageLds<D>& ST, uint32_t m, const float (&st)[LobeLayout<D>::DH],
+                                               const float (&b)[LobeLayout<D>::DH], float (&t)[LobeLayout<D>::DH]) {
+    using LL = LobeLayout<D>;
+    const uint32_t h = lane_id() / LL::LPG;
+    const float* y = &ST.y[m][h * LL::DH];
+    float e = 0.0f;
+#pragma unroll
+    for (int jj = 0; jj < LL::DH; ++jj) {
+        t[jj] = fmaf(y[jj], st[jj], b[jj]);
+        e = fmaf(t[jj], t[jj], e);
+    }
+    if constexpr (LL::H == 2) e += __shfl_xor(e, 32, kWave);
+    return e;
+}
+
+// ---------------------------------------------------------- lobes forward ----
+
+template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK>
+__global__ __launch_bounds__(kBlock) void lobes_fwd(Args a) {
+    using LL = LobeLayout<D>;
+    __shared__ SamplerLds<D> S;
+    __shared__ PixelLds<D> PXs[kWavesPerBlock];
+    __shared__ StageLds<D> STs[kWavesPerBlock];
+    __shared__ float RES[kWavesPerBlock][kTile];
+    stage_sampler<D, SK, NUS>(S, a);
+    __syncthreads();
+    const uint32_t wv = threadIdx.x >> 6;
+    PixelLds<D>& PX = PXs[wv];
+    StageLds<D>& ST = STs[wv];
+    float* res = RES[wv];
+    const uint32_t lane = lane_id();
+    const uint32_t half = lane / LL::LPG;
+    const uint32_t groups = (a.L + LL::LPG - 1) / LL::LPG;
+    for_each_task(a, [&](uint32_t task) {
+        const TileInfo ti = tile_info(a, task);
+        res[lane] = 0.0f;
+        wave_sync();
+        for (uint32_t kg = 0; kg < groups; ++kg) {
+            float st[LL::DH], b[LL::DH], w;
+            uint32_t lobe;
+            bool own;
+            load_lobe<D>(a, kg, st, b, &w, &lobe, &own);
+            if (half != 0) w = 0.0f;  // both halves form G; one adds w G
+            float acc = 0.0f;
+            uint32_t cur = 0xFFFFFFFFu;
+            auto flush = [&]() {
+                if (cur != 0xFFFFFFFFu) {
+                    const float s = wave_sum(acc);
+                    if (lane == 0) res[cur] += s;
+                }
+                acc = 0.0f;
+            };
+            walk_tile<D, SK, NUS, SHIFT, BACK, true>(
+                a, S, PX, task, ti.n, ti.inb, ti.off, ti.total, [&](uint32_t) {},
+                [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t, bool, uint32_t, uint32_t) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) ST.y[lane][j] = x[j];
+                    ST.q[lane] = q;
+                    wave_sync();
+                    for (uint32_t m = 0; m < count; ++m) {
+                        const uint32_t qm = ST.q[m];
+                        if (qm != cur) {
+                            flush();
+                            cur = qm;
+                        }
+                        float t[LL::DH];
+                        const float e = lobe_exponent<D>(ST, m, st, b, t);
+                        acc = fmaf(w, exp2f(-e), acc);
+                    }
+                    wave_sync();
+                },
+                [&](uint32_t) {});
+            flush();
+            wave_sync();
+        }
+        if (ti.inb) write_pixel(a, ti.p, res[lane]);
+        wave_sync();
+    });
+}
+
+// ---------------------------------------------------------- lobes adjoint ----
+
+template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK>
+__global__ __launch_bounds__(kBlock) void lobes_bwd(Args a) {
+    using LL = LobeLayout<D>;
+    __shared__ SamplerLds<D> S;
+    __shared__ PixelLds<D> PXs[kWavesPerBlock];
+    __shared__ StageLds<D> STs[kWavesPerBlock];
+    stage_sampler<D, SK, NUS>(S, a);
+    __syncthreads();
+    const uint32_t wv = threadIdx.x >> 6;
+    PixelLds<D>& PX = PXs[wv];
+    StageLds<D>& ST = STs[wv];
+    const uint32_t lane = lane_id();
+    const uint32_t half = lane / LL::LPG;
+    const uint32_t groups = (a.L + LL::LPG - 1) / LL::LPG;
+    for_each_task(a, [&](uint32_t task) {
+        const TileInfo ti = tile_info(a, task);
+        const uint32_t N = ti.inb ? a.counts[ti.p] : 0u;
+        const float gscale = (ti.inb && N) ? a.grad_means[ti.p] / static_cast<float>(N) : 0.0f;
+        for (uint32_t kg = 0; kg < groups; ++kg) {
+            float st[LL::DH], b[LL::DH], w;
+            uint32_t lobe;
+            bool own;
+            load_lobe<D>(a, kg, st, b, &w, &lobe, &own);
+            float acc_c[LL::DH], acc_l[LL::DH], acc_w = 0.0f;
+#pragma unroll
+            for (int jj = 0; jj < LL::DH; ++jj) acc_c[jj] = acc_l[jj] = 0.0f;
+            walk_tile<D, SK, NUS, SHIFT, BACK, true>(
+                a, S, PX, task, ti.n, ti.inb, ti.off, ti.total, [&](uint32_t) {},
+                [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t, bool, uint32_t, uint32_t) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) ST.y[lane][j] = x[j];
+                    ST.scale[lane] = __shfl(gscale, q, kWave);
+                    wave_sync();
+                    for (uint32_t m = 0; m < count; ++m) {
+                        float t[LL::DH];
+                        const float e = lobe_exponent<D>(ST, m, st, b, t);
+                        const float aG = ST.scale[m] * exp2f(-e);
+                        acc_w += aG;
+                        const float gw = aG * w;
+#pragma unroll
+                        for (int jj = 0; jj < LL::DH; ++jj) {
+                            const float gt = gw * t[jj];
+                            acc_c[jj] += gt;
+                            acc_l[jj] = fmaf(gt, t[jj], acc_l[jj]);
+                        }
+                    }
+                    wave_sync();
+                },
+                [&](uint32_t) {});
+            if (own) {
+                float* out = a.partials + uint64_t(task) * a.n_theta;
+                const uint32_t d = a.d, L = a.L;
+#pragma unroll
+                for (int jj = 0; jj < LL::DH; ++jj) {
+                    const uint32_t j = half * LL::DH + jj;
+                    if (j < d) {
+                        out[lobe * d + j] = acc_c[jj] * st[jj];
+                        out[L * d + lobe * d + j] = acc_l[jj];
+                    }
+                }
+                if (half == 0) out[2 * L * d + lobe] = acc_w;
+            }
+        }
+    });
+}
+
+// First reduction level: block (x = 64-parameter tile, y = chunk of kChunkTasks tasks) sums
+// its tasks in FP64; wave w takes tasks w, w+4, ... of the chunk and the four wave sums are
+// combined in wave order.  Output: chunk_sums[chunk][e].
+__global__ __launch_bounds__(256) void reduce_partials_chunks(const float* __restrict__ partials,
+                                                              uint32_t num_tasks, uint32_t n_theta,
+                                                              double* __restrict__ chunk_sums) {
+    __shared__ double part[4][64];
+    const uint32_t e = blockIdx.x * 64 + (threadIdx.x & 63u);
+    const uint32_t w = threadIdx.x >> 6;
+    const uint32_t t0 = blockIdx.y * kChunkTasks;
+    const uint32_t t1 = min(t0 + kChunkTasks, num_tasks);
+    double acc = 0.0;
+    if (e < n_theta)
+        for (uint32_t t = t0 + w; t < t1; t += 4) acc += static_cast<double>(partials[uint64_t(t) * n_theta + e]);
+    part[w][threadIdx.x & 63u] = acc;
+    __syncthreads();
+    if (w == 0 && e < n_theta) {
+        const uint32_t l = threadIdx.x & 63u;
+        chunk_sums[uint64_t(blockIdx.y) * n_theta + e] = ((part[0][l] + part[1][l]) + part[2][l]) + part[3][l];
+    }
+}
+
+// Second level: grad[e] += scale_e * sum over chunks in chunk order; the centre and log-width
+// entries carry the factor 1/kKappa^2 of the exp2 form.
+__global__ void reduce_chunks(const double* __restrict__ chunk_sums, uint32_t num_chunks, uint32_t n_theta,
+                              uint32_t LD, float* __restrict__ grad) {
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_theta) return;
+    double acc = 0.0;
+    for (uint32_t c = 0; c < num_chunks; ++c) acc += chunk_sums[uint64_t(c) * n_theta + e];
+    const double scale = e < 2 * LD ? 1.0 / (static_cast<double>(kKappa) * kKappa) : 1.0;
+    grad[e] += static_cast<float>(acc * scale);
+}
+
+__global__ void reset_queue(uint32_t* q) { *q = 0u; }
+
+// ------------------------------------------------ materialised samples (plain) ----
+
+template <uint32_t SK, bool NUS, bool SHIFT, bool BACK>
+__global__ __launch_bounds__(kBlock) void pixel_samples(Args a) {
+    constexpr int D = QMC_MAX_DIMS;
+    __shared__ SamplerLds<D> S;
+    __shared__ PixelLds<D> PXs[kWavesPerBlock];
+    stage_sampler<D, SK, NUS>(S, a);
+    __syncthreads();
+    PixelLds<D>& PX = PXs[threadIdx.x >> 6];
+    const uint32_t lane = lane_id();
+    for_each_task(a, [&](uint32_t task) {
+        const TileInfo ti = tile_info(a, task);
+        walk_tile<D, SK, NUS, SHIFT, BACK, false>(
+            a, S, PX, task, ti.n, ti.inb, ti.off, ti.total, [&](uint32_t) {},
+            [&](const float (&x)[D], uint32_t count, uint32_t, uint32_t pp, bool, uint32_t, uint32_t i) {
+                if (lane < count) {
+                    const uint64_t off = a.offsets[pp] + i;
+#pragma unroll
+                    for (int j = 0; j < D; ++j)
+                        if (uint32_t(j) < a.d) a.out[uint64_t(j) * a.out_ld + off] = x[j];
+                }
+            },
+            [&](uint32_t) {});
+    });
+}
+
+// Exclusive scan of counts into u64 offsets: per-block scans of 1024 counts, a scan of the
+// block totals, then the block prefixes are added.
+__global__ __launch_bounds__(256) void scan_blocks(const uint32_t* __restrict__ counts, uint32_t n,
+                                                   uint64_t* __restrict__ offsets, uint64_t* __restrict__ block_tot) {
+    __shared__ uint64_t part[256];
+    const uint32_t base = blockIdx.x * 1024 + threadIdx.x * 4;
+    uint64_t v[4], run = 0;
+    for (int r = 0; r < 4; ++r) {
+        v[r] = base + r < n ? counts[base + r] : 0u;
+        run += v[r];
+    }
+    part[threadIdx.x] = run;
+    __syncthreads();
+    for (uint32_t o = 1; o < 256; o <<= 1) {
+        const uint64_t add = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint64_t ex = part[threadIdx.x] - run;
+    for (int r = 0; r < 4; ++r) {
+        if (base + r < n) offsets[base + r] = ex;
+        ex += v[r];
+    }
+    if (threadIdx.x == 255) block_tot[blockIdx.x] = part[255];
+}
+
+__global__ void scan_totals(uint64_t* __restrict__ block_tot, uint32_t nblocks, uint64_t* __restrict__ offsets,
+                            uint32_t n) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint64_t run = 0;
+    for (uint32_t b = 0; b < nblocks; ++b) {
+        const uint64_t t = block_tot[b];
+        block_tot[b] = run;
+        run += t;
+    }
+    offsets[n] = run;
+}
+
+__global__ __launch_bounds__(256) void scan_add(uint64_t* __restrict__ offsets, uint32_t n,
+                                                const uint64_t* __restrict__ block_tot) {
+    const uint32_t e = blockIdx.x * 256 + threadIdx.x;
+    if (e < n) offsets[e] += block_tot[e / 1024];
+}
+
+// -------------------------------------------------------------------- host ----
+
+struct Plan {
+    size_t queue_off = 0, partials_off = 256, chunks_off = 256, total = 256;
+    uint32_t num_tasks = 0, num_chunks = 0, n_theta = 0;
+};
+
+Plan make_plan(const qmc_integrand* ig, uint32_t P, bool backward) {
+    Plan pl;
+    pl.num_tasks = (P + kTile - 1) / kTile;
+    pl.num_chunks = (pl.num_tasks + kChunkTasks - 1) / kChunkTasks;
+    if (ig && ig->kind == QMC_F_LOBES) pl.n_theta = ig->num_lobes * (2 * ig->d + 1);
+    if (backward) {
+        pl.chunks_off = (pl.partials_off + size_t(pl.num_tasks) * pl.n_theta * 4 + 255) & ~size_t(255);
+        pl.total = pl.chunks_off + size_t(pl.num_chunks) * pl.n_theta * 8;
+    }
+    return pl;
+}
+
+qmc_status validate_sampler(const char* who, const qmc_sampler* sp, uint32_t d) {
+    if (sp->kind < QMC_SAMPLER_SOBOL || sp->kind > QMC_SAMPLER_POINTS)
+        return fail(QMC_ERR_INVALID_ARGUMENT, "%s: unknown sampler kind %u", who, sp->kind);
+    if (!sp->table) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: sampler table is NULL", who);
+    if (sp->s == 0 || sp->s > QMC_MAX_DIMS) return fail(QMC_ERR_OUT_OF_RANGE, "%s: sampler s out of range", who);
+    const uint32_t allowed = QMC_PIXEL_NUS | QMC_PIXEL_SHIFT | QMC_SHIFT_XOR | QMC_LATTICE_BACKWARD;
+    if (sp->flags & ~allowed) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: unknown sampler flags", who);
+    if (sp->kind != QMC_SAMPLER_SOBOL && (sp->flags & QMC_PIXEL_NUS))
+        return fail(QMC_ERR_INVALID_ARGUMENT, "%s: only the Sobol' sampler has a nested scramble", who);
+    if (sp->kind == QMC_SAMPLER_POINTS && !sp->offsets)
+        return fail(QMC_ERR_INVALID_ARGUMENT, "%s: POINTS sampler needs offsets", who);
+    if (d > sp->s) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: integrand needs d = %u > sampler s = %u", who, d, sp->s);
+    return QMC_OK;
+}
+
+qmc_status validate(const char* who, qmc_context ctx, const qmc_sampler* sp, const qmc_integrand* ig, uint32_t W,
+                    uint32_t H, const uint32_t* counts, uint32_t begin, uint32_t end, bool backward) {
+    if (!ctx || !sp || !ig) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: NULL context, sampler or integrand", who);
+    if (ig->kind == QMC_F_GENZ) {
+        if (ig->d != 8) return fail(QMC_ERR_UNSUPPORTED, "%s: the Genz integrand has d = 8", who);
+        if (!ig->pixel_params) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: Genz pixel_params is NULL", who);
+        if (backward) return fail(QMC_ERR_UNSUPPORTED, "%s: the adjoint exists for the lobe integrand only", who);
+    } else if (ig->kind == QMC_F_LOBES) {
+        if (ig->d == 0 || ig->d > QMC_MAX_DIMS) return fail(QMC_ERR_OUT_OF_RANGE, "%s: lobe dimension out of range", who);
+        if (ig->num_lobes == 0 || ig->num_lobes > 65536)
+            return fail(QMC_ERR_OUT_OF_RANGE, "%s: num_lobes out of range", who);
+        if (!ig->params) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: lobe params is NULL", who);
+    } else {
+        return fail(QMC_ERR_INVALID_ARGUMENT, "%s: unknown integrand kind %u", who, ig->kind);
+    }
+    qmc_status st = validate_sampler(who, sp, ig->d);
+    if (st != QMC_OK) return st;
+    if (uint64_t(W) * H == 0 || uint64_t(W) * H > 0xFFFFFFFFull - kTile)
+        return fail(QMC_ERR_OUT_OF_RANGE, "%s: image size out of range", who);
+    if (!counts) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: counts is NULL", who);
+    if (begin > end) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: sample_begin > sample_end", who);
+    return QMC_OK;
+}
+
+// Launches Fam::go<SK, NUS, SHIFT, BACK> for the sampler's kind and flags; only the
+// meaningful combinations are instantiated (scrambling for Sobol' only, backward order for
+// the lattice only, materialised points without either).
+template <typename Fam>
+void dispatch_sampler(uint32_t skind, bool nus, bool shift, bool back, uint32_t grid, hipStream_t hs, const Args& a) {
+    if (skind == QMC_SAMPLER_SOBOL) {
+        if (nus) {
+            if (shift) Fam::template go<QMC_SAMPLER_SOBOL, true, true, false>(grid, hs, a);
+            else Fam::template go<QMC_SAMPLER_SOBOL, true, false, false>(grid, hs, a);
+        } else {
+            if (shift) Fam::template go<QMC_SAMPLER_SOBOL, false, true, false>(grid, hs, a);
+            else Fam::template go<QMC_SAMPLER_SOBOL, false, false, false>(grid, hs, a);
+        }
+    } else if (skind == QMC_SAMPLER_LATTICE) {
+        if (back) {
+            if (shift) Fam::template go<QMC_SAMPLER_LATTICE, false, true, true>(grid, hs, a);
+            else Fam::template go<QMC_SAMPLER_LATTICE, false, false, true>(grid, hs, a);
+        } else {
+            if (shift) Fam::template go<QMC_SAMPLER_LATTICE, false, true, false>(grid, hs, a);
+            else Fam::template go<QMC_SAMPLER_LATTICE, false, false, false>(grid, hs, a);
+        }
+    } else if constexpr (Fam::kPoints) {
+        Fam::template go<QMC_SAMPLER_POINTS, false, false, false>(grid, hs, a);
+    }
+}
+
+struct GenzFam {
+    static constexpr bool kPoints = true;
+    template <uint32_t SK, bool NUS, bool SH, bool BK>
+    static void go(uint32_t grid, hipStream_t hs, const Args& a) {
+        hipLaunchKernelGGL((genz_fwd<SK, NUS, SH, BK>), dim3(grid), dim3(kBlock), 0, hs, a);
+    }
+};
+
+template <int D>
+struct LobesFwdFam {
+    static constexpr bool kPoints = true;
+    template <uint32_t SK, bool NUS, bool SH, bool BK>
+    static void go(uint32_t grid, hipStream_t hs, const Args& a) {
+        hipLaunchKernelGGL((lobes_fwd<D, SK, NUS, SH, BK>), dim3(grid), dim3(kBlock), 0, hs, a);
+    }
+};
+
+template <int D>
+struct LobesBwdFam {
+    static constexpr bool kPoints = true;
+    template <uint32_t SK, bool NUS, bool SH, bool BK>
+    static void go(uint32_t grid, hipStream_t hs, const Args& a) {
+        hipLaunchKernelGGL((lobes_bwd<D, SK, NUS, SH, BK>), dim3(grid), dim3(kBlock), 0, hs, a);
+    }
+};
+
+struct SamplesFam {
+    static constexpr bool kPoints = false;
+    template <uint32_t SK, bool NUS, bool SH, bool BK>
+    static void go(uint32_t grid, hipStream_t hs, const Args& a) {
+        hipLaunchKernelGGL((pixel_samples<SK, NUS, SH, BK>), dim3(grid), dim3(kBlock), 0, hs, a);
+    }
+};
+
+Args base_args(const qmc_sampler* sp, uint32_t d, uint32_t P, const uint32_t* counts, uint32_t begin, uint32_t end) {
+    Args a{};
+    a.skind = sp->kind;
+    a.s = sp->s;
+    a.seed = sp->seed;
+    a.sflags = sp->flags;
+    a.sxor = (sp->flags & QMC_SHIFT_XOR) ? 1u : 0u;
+    a.table = static_cast<const uint32_t*>(sp->table);
+    a.points = static_cast<const float*>(sp->table);
+    a.points_ld = sp->points_ld;
+    a.offsets = sp->offsets;
+    a.d = d;
+    a.num_pixels = P;
+    a.counts = counts;
+    a.begin = begin;
+    a.end = end;
+    a.aligned = (begin % kWave) == 0 ? 1u : 0u;
+    a.num_tasks = (P + kTile - 1) / kTile;
+    return a;
+}
+
+uint32_t persistent_grid(const qmc_context ctx, const IntegrateTune& tn, uint32_t num_tasks, Args* a) {
+    const uint32_t waves_wanted = std::max<uint32_t>(1, uint32_t(ctx->num_cus) * tn.waves_per_cu);
+    const uint32_t task_waves = ((num_tasks + kWavesPerBlock - 1) / kWavesPerBlock) * kWavesPerBlock;
+    const uint32_t waves = std::min<uint32_t>(waves_wanted, std::max<uint32_t>(task_waves, kWavesPerBlock));
+    const uint32_t grid = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    a->total_waves = grid * kWavesPerBlock;
+    a->dynamic = tn.dynamic;
+    return grid;
+}
+
+qmc_status integrate_common(const char* who, qmc_context ctx, qmc_stream stream, const qmc_sampler* sp,
+                            const qmc_integrand* ig, uint32_t W, uint32_t H, const uint32_t* counts, uint32_t begin,
+                            uint32_t end, float* sums, float* means, const float* grad_means, float* grad_params,
+                            void* ws, size_t ws_bytes, bool backward) {
+    qmc_status st = validate(who, ctx, sp, ig, W, H, counts, begin, end, backward);
+    if (st != QMC_OK) return st;
+    if (!backward && !sums && !means) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: sums and means are both NULL", who);
+    if (backward && (!grad_means || !grad_params))
+        return fail(QMC_ERR_INVALID_ARGUMENT, "%s: grad_means and grad_params are required", who);
+    const uint32_t P = W * H;
+    const Plan pl = make_plan(ig, P, backward);
+    if (!ws || ws_bytes < pl.total)
+        return fail(QMC_ERR_WORKSPACE, "%s: workspace of %zu bytes needed, %zu given", who, pl.total, ws_bytes);
+    DeviceGuard guard(ctx->device);
+    if (guard.status != QMC_OK) return guard.status;
+    hipStream_t hs = as_stream(stream);
+    Args a = base_args(sp, ig->d, P, counts, begin, end);
+    a.fkind = ig->kind;
+    a.L = ig->num_lobes;
+    a.pixel_seed = ig->pixel_seed;
+    a.params = ig->params;
+    a.pixel_params = ig->pixel_params;
+    a.sums = sums;
+    a.means = means;
+    a.grad_means = grad_means;
+    a.queue = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.queue_off);
+    a.partials = reinterpret_cast<float*>(static_cast<char*>(ws) + pl.partials_off);
+    a.n_theta = pl.n_theta;
+    const uint32_t grid = persistent_grid(ctx, integrate_tune(ctx, ig->kind, ig->d, backward), pl.num_tasks, &a);
+    const bool nus = (sp->flags & QMC_PIXEL_NUS) != 0, shift = (sp->flags & QMC_PIXEL_SHIFT) != 0;
+    const bool back = (sp->flags & QMC_LATTICE_BACKWARD) != 0;
+    clear_launch_error();
+    if (a.dynamic) hipLaunchKernelGGL(reset_queue, dim3(1), dim3(1), 0, hs, a.queue);
+    if (!backward) {
+        if (ig->kind == QMC_F_GENZ)
+            dispatch_sampler<GenzFam>(sp->kind, nus, shift, back, grid, hs, a);
+        else if (ig->d <= 8)
+            dispatch_sampler<LobesFwdFam<8>>(sp->kind, nus, shift, back, grid, hs, a);
+        else
+            dispatch_sampler<LobesFwdFam<64>>(sp->kind, nus, shift, back, grid, hs, a);
+    } else {
+        if (ig->d <= 8)
+            dispatch_sampler<LobesBwdFam<8>>(sp->kind, nus, shift, back, grid, hs, a);
+        else
+            dispatch_sampler<LobesBwdFam<64>>(sp->kind, nus, shift, back, grid, hs, a);
+        double* chunk_sums = reinterpret_cast<double*>(static_cast<char*>(ws) + pl.chunks_off);
+        hipLaunchKernelGGL(reduce_partials_chunks, dim3((pl.n_theta + 63) / 64, pl.num_chunks), dim3(256), 0, hs,
+                           a.partials, pl.num_tasks, pl.n_theta, chunk_sums);
+        hipLaunchKernelGGL(reduce_chunks, dim3((pl.n_theta + 255) / 256), dim3(256), 0, hs, chunk_sums,
+                           pl.num_chunks, pl.n_theta, ig->num_lobes * ig->d, grad_params);
+    }
+    return check_launch(who);
+}
+
+}  // namespace
+}  // namespace qmc
+
+using namespace qmc;
+
+extern "C" qmc_status qmc_workspace_size(qmc_context ctx, const qmc_sampler* sampler, const qmc_integrand* integrand,
+                                         uint32_t width, uint32_t height, int backward, size_t* bytes) {
+    if (!ctx || !sampler || !integrand || !bytes)
+        return fail(QMC_ERR_INVALID_ARGUMENT, "qmc_workspace_size: NULL argument");
+    *bytes = make_plan(integrand, width * height, backward != 0).total;
+    return QMC_OK;
+}
+
+extern "C" qmc_status qmc_integrate_pixels(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
+                                           const qmc_integrand* integrand, uint32_t width, uint32_t height,
+                                           const uint32_t* counts, uint32_t sample_begin, uint32_t sample_end,
+                                           float* sums, float* means, void* workspace, size_t workspace_bytes) {
+    return integrate_common("qmc_integrate_pixels", ctx, stream, sampler, integrand, width, height, counts,
+                            sample_begin, sample_end, sums, means, nullptr, nullptr, workspace, workspace_bytes,
+                            false);
+}
+
+extern "C" qmc_status qmc_integrate_pixels_backward(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
+                                                    const qmc_integrand* integrand, uint32_t width, uint32_t height,
+                                                    const uint32_t* counts, uint32_t sample_begin,
+                                                    uint32_t sample_end, const float* grad_means, float* grad_params,
+                                                    void* workspace, size_t workspace_bytes) {
+    return integrate_common("qmc_integrate_pixels_backward", ctx, stream, sampler, integrand, width, height, counts,
+                            sample_begin, sample_end, nullptr, nullptr, grad_means, grad_params, workspace,
+                            workspace_bytes, true);
+}
+
+extern "C" qmc_status qmc_sample_offsets(qmc_context ctx, qmc_stream stream, const uint32_t* counts,
+                                         uint32_t num_pixels, uint64_t* offsets, void* workspace,
+                                         size_t workspace_bytes) {
+    const char* who = "qmc_sample_offsets";
+    if (!ctx || !counts || !offsets || !workspace) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: NULL argument", who);
+    if (num_pixels == 0) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: num_pixels is 0", who);
+    const uint32_t nblocks = (num_pixels + 1023) / 1024;
+    if (workspace_bytes < size_t(nblocks) * 8)
+        return fail(QMC_ERR_WORKSPACE, "%s: workspace of %zu bytes needed", who, size_t(nblocks) * 8);
+    DeviceGuard guard(ctx->device);
+    if (guard.status != QMC_OK) return guard.status;
+    hipStream_t hs = as_stream(stream);
+    uint64_t* tot = static_cast<uint64_t*>(workspace);
+    clear_launch_error();
+    hipLaunchKernelGGL(scan_blocks, dim3(nblocks), dim3(256), 0, hs, counts, num_pixels, offsets, tot);
+    hipLaunchKernelGGL(scan_totals, dim3(1), dim3(64), 0, hs, tot, nblocks, offsets, num_pixels);
+    hipLaunchKernelGGL(scan_add, dim3((num_pixels + 255) / 256), dim3(256), 0, hs, offsets, num_pixels, tot);
+    return check_launch(who);
+}
+
+extern "C" qmc_status qmc_generate_pixel_samples(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
+                                                 uint32_t d, uint32_t width, uint32_t height, const uint32_t* counts,
+                                                 const uint64_t* offsets, float* out, uint64_t ld,
+                                                 void* workspace, size_t workspace_bytes) {
+    const char* who = "qmc_generate_pixel_samples";
+    if (!ctx || !sampler || !counts || !offsets || !out) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: NULL argument", who);
+    if (sampler->kind == QMC_SAMPLER_POINTS) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: sampler must generate", who);
+    if (d == 0 || d > QMC_MAX_DIMS) return fail(QMC_ERR_OUT_OF_RANGE, "%s: d out of range", who);
+    qmc_status st = validate_sampler(who, sampler, d);
+    if (st != QMC_OK) return st;
+    if (uint64_t(width) * height == 0 || uint64_t(width) * height > 0xFFFFFFFFull - kTile)
+        return fail(QMC_ERR_OUT_OF_RANGE, "%s: image size out of range", who);
+    if (!workspace || workspace_bytes < 256) return fail(QMC_ERR_WORKSPACE, "%s: 256 bytes of workspace needed", who);
+    DeviceGuard guard(ctx->device);
+    if (guard.status != QMC_OK) return guard.status;
+    hipStream_t hs = as_stream(stream);
+    const uint32_t P = width * height;
+    Args a = base_args(sampler, d, P, counts, 0u, 0xFFFFFFFFu);
+    a.offsets = offsets;
+    a.out = out;
+    a.out_ld = ld;
+    a.queue = static_cast<uint32_t*>(workspace);
+    IntegrateTune tn;
+    const uint32_t grid = persistent_grid(ctx, tn, a.num_tasks, &a);
+    const bool nus = (sampler->flags & QMC_PIXEL_NUS) != 0, shift = (sampler->flags & QMC_PIXEL_SHIFT) != 0;
+    const bool back = (sampler->flags & QMC_LATTICE_BACKWARD) != 0;
+    clear_launch_error();
+    if (a.dynamic) hipLaunchKernelGGL(reset_queue, dim3(1), dim3(1), 0, hs, a.queue);
+    dispatch_sampler<SamplesFam>(sampler->kind, nus, shift, back, grid, hs, a);
+    return check_launch(who);
+}

@@ -1,0 +1,192 @@
+"""GPU parity of point generation against the CPU oracle (bit-exact, Sec. 2.1-2.4)."""
+
+import os
+
+import numpy as np
+import pytest
+
+from _exhaustive import compare_slice
+from oracle import digital, generate
+from oracle.unifloat import map_u32_to_unifloat_bits
+from synth import cp_shifts, lattice_vector, nus_seeds, pick, sobol_direction_init
+
+pytestmark = pytest.mark.gpu
+
+XOR = generate.SHIFT_XOR
+BACK = generate.LATTICE_BACKWARD
+
+
+def _mats(s):
+    return digital.sobol_matrices(s, sobol_direction_init(s, 0))
+
+
+def _run_sobol(q, s, first, n, nus, shift, flags=0, ld=None, want_u32=True, want_f32=True):
+    import torch
+
+    mats = _mats(s)
+    dm = q.from_u32(mats)
+    ds = q.from_u32(nus_seeds(s, 1)) if nus else None
+    dh = q.from_u32(cp_shifts(s, 2)) if shift else None
+    u, f = q.qmc_generate_sobol(dm, first, n, ds, dh, flags, ld=ld, want_u32=want_u32, want_f32=want_f32)
+    torch.cuda.synchronize()
+    ld = n if ld is None else ld
+    gu = q.to_u32(u)[:, :n] if u is not None else None
+    gf = f.cpu().numpy()[:, :n].view(np.uint32) if f is not None else None
+    eu, ef = generate.generate_sobol(mats, first, n, nus_seeds(s, 1) if nus else None,
+                                     cp_shifts(s, 2) if shift else None, flags)
+    return gu, gf, eu, ef.view(np.uint32)
+
+
+SOBOL_CASES = [
+    # s, first, n, nus, shift, flags, ld
+    (4, 0, 1 << 16, False, False, 0, None),               # unscrambled (0,2)-sequence + 2 dims
+    (32, 0, 3 * 2048 + 77, True, True, 0, None),          # several wave runs and a ragged tail
+    (32, 4 * 12345, 70001, True, True, XOR, None),        # aligned start, not on a 256 boundary
+    (7, 1001, 5000, True, True, 0, None),                 # unaligned start: general kernel
+    (5, 0, 100, False, True, 0, None),                    # shift only
+    (6, 64, 999, True, False, 0, None),                   # scramble only
+    (64, (1 << 32) - 5000, 5000, True, True, 0, None),    # the end of the 32-bit index range
+    (9, 256, 3000, True, True, 0, 3004),                  # ld > n, aligned
+    (9, 256, 3000, True, True, XOR, 3001),                # odd ld: general kernel
+    (3, 12, 1, True, True, 0, None),                      # a single point
+]
+
+
+@pytest.mark.parametrize("case", SOBOL_CASES, ids=[str(c[:3]) for c in SOBOL_CASES])
+def test_sobol_bit_exact(qmc, case):
+    s, first, n, nus, shift, flags, ld = case
+    gu, gf, eu, ef = _run_sobol(qmc, s, first, n, nus, shift, flags, ld)
+    assert np.array_equal(gu, eu)
+    assert np.array_equal(gf, ef)
+
+
+def test_sobol_single_output_variants(qmc):
+    gu, gf, eu, ef = _run_sobol(qmc, 8, 0, 4096 + 3, True, True, want_f32=False)
+    assert gf is None and np.array_equal(gu, eu)
+    gu, gf, eu, ef = _run_sobol(qmc, 8, 0, 4096 + 3, True, True, want_u32=False)
+    assert gu is None and np.array_equal(gf, ef)
+
+
+def test_sobol_gpu_output_is_02_net(qmc):
+    from test_oracle_digital import net_t_value
+
+    gu, _, _, _ = _run_sobol(qmc, 2, 0, 1 << 16, True, False)
+    x, y = gu[0].astype(np.uint64), gu[1].astype(np.uint64)
+    for m in range(17):
+        nn = 1 << m
+        for b in range(min(2, (1 << 16) // nn)):
+            sl = slice(b * nn, (b + 1) * nn)
+            assert net_t_value(x[sl], y[sl], m) == 0, (m, b)
+
+
+def _run_lattice(q, s, bits, first, n, shift, flags=0, ld=None):
+    import torch
+
+    g = lattice_vector(s, bits, 3)
+    dh = q.from_u32(cp_shifts(s, 2)) if shift else None
+    u, f = q.qmc_generate_lattice(q.from_u32(g), first, n, dh, flags, ld=ld)
+    torch.cuda.synchronize()
+    eu, ef = generate.generate_lattice(g, first, n, cp_shifts(s, 2) if shift else None, flags)
+    return q.to_u32(u)[:, :n], f.cpu().numpy()[:, :n].view(np.uint32), eu, ef.view(np.uint32)
+
+
+LATTICE_CASES = [
+    (32, 20, 0, 1 << 20, False, 0, None),        # rank-1 lattice sequence n = 2^20, s = 32
+    (32, 20, 0, 1 << 20, True, 0, None),         # with an integer Cranley-Patterson rotation
+    (16, 30, 4 * 777, 100003, True, XOR, None),
+    (16, 30, 0, 70000, False, BACK, None),       # backward enumeration
+    (5, 20, (1 << 32) - 4099, 4099, True, BACK, None),
+    (7, 20, 3, 5000, True, 0, None),             # unaligned: general kernel
+    (7, 20, 8, 5000, True, BACK | XOR, 5003),
+]
+
+
+@pytest.mark.parametrize("case", LATTICE_CASES, ids=[str(c[:4]) for c in LATTICE_CASES])
+def test_lattice_bit_exact(qmc, case):
+    s, bits, first, n, shift, flags, ld = case
+    gu, gf, eu, ef = _run_lattice(qmc, s, bits, first, n, shift, flags, ld)
+    assert np.array_equal(gu, eu)
+    assert np.array_equal(gf, ef)
+
+
+def test_lattice_backward_origin_last(qmc):
+    gu, gf, _, _ = _run_lattice(qmc, 4, 20, (1 << 32) - 4, 4, False, BACK)
+    assert np.all(gu[:, -1] == 0) and np.all(gf[:, -1] == 0)
+
+
+def test_full_size_scrambled_sobol_sampled(qmc):
+    """2^24 points x 32 dims, scramble + rotation, in the benchmark's launch configuration;
+    compared on 2^15 random (i, j) samples plus the first and last 1024 indices of every dim."""
+    import torch
+
+    s, n = 32, 1 << 24
+    mats = _mats(s)
+    seeds, shifts = nus_seeds(s, 1), cp_shifts(s, 2)
+    u, f = qmc.qmc_generate_sobol(qmc.from_u32(mats), 0, n, qmc.from_u32(seeds), qmc.from_u32(shifts), 0)
+    flat = pick(s * n, 1 << 15, 31)
+    jj, ii = flat // n, flat % n
+    edges = np.concatenate([np.arange(1024), np.arange(n - 1024, n)])
+    sel_i = torch.from_numpy(np.concatenate([ii, np.tile(edges, s)])).cuda()
+    sel_j = torch.from_numpy(np.concatenate([jj, np.repeat(np.arange(s), edges.size)])).cuda()
+    gu = u[sel_j, sel_i].cpu().numpy().view(np.uint32)
+    gf = f[sel_j, sel_i].cpu().numpy().view(np.uint32)
+    torch.cuda.synchronize()
+    si, sj = sel_i.cpu().numpy(), sel_j.cpu().numpy()
+    want = np.zeros(si.size, np.uint32)
+    for j in range(s):
+        m = sj == j
+        want[m] = generate.sobol_at(mats, si[m], seeds, shifts, 0, dims=[j])[0]
+    assert np.array_equal(gu, want)
+    assert np.array_equal(gf, map_u32_to_unifloat_bits(want))
+    del u, f
+
+
+def test_map_u32_to_unifloat_exhaustive(qmc):
+    """All 2^32 inputs, as in the paper's own check of the conversion (Sec. 2.1)."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+
+    import torch
+
+    chunk = 1 << 27
+    workers = min(16, os.cpu_count() or 1)
+    ctx = mp.get_context("spawn")
+    shm = shared_memory.SharedMemory(create=True, size=chunk * 4)
+    host = np.ndarray((chunk,), dtype=np.uint32, buffer=shm.buf)
+    try:
+        with ctx.Pool(workers) as pool:
+            for start in range(0, 1 << 32, chunk):
+                base = torch.arange(start, start + chunk, dtype=torch.int64, device="cuda")
+                inp = torch.where(base >= (1 << 31), base - (1 << 32), base).to(torch.int32)
+                out = qmc.qmc_map_u32_to_unifloat(inp)
+                host[:] = out.view(torch.int32).cpu().numpy().view(np.uint32)
+                step = chunk // workers
+                jobs = [(shm.name, chunk, start, k * step, chunk if k == workers - 1 else (k + 1) * step)
+                        for k in range(workers)]
+                for nbad, first_bad in pool.map(compare_slice, jobs):
+                    assert nbad == 0, "mismatch at u=0x%08x" % first_bad
+                assert float(out.max()) < 1.0
+    finally:
+        del host
+        shm.close()
+        shm.unlink()
+
+
+def test_argument_errors(qmc):
+    import torch
+
+    dm = qmc.from_u32(_mats(4))
+    with pytest.raises(qmc.QMCError) as e:
+        qmc.qmc_generate_sobol(dm, (1 << 32) - 10, 11)
+    assert e.value.status == 2
+    with pytest.raises(qmc.QMCError) as e:
+        qmc.qmc_generate_sobol(dm, 0, 100, flags=8)
+    assert e.value.status == 1
+    out = torch.empty((4, 100), dtype=torch.float32, device="cuda")
+    with pytest.raises(qmc.QMCError) as e:
+        qmc.qmc_generate_sobol(dm, 0, 100, out_u32=out.view(torch.int32), out_f32=out)
+    assert e.value.status == 1
+    big = qmc.from_u32(np.zeros((65, 32), np.uint32))
+    with pytest.raises(qmc.QMCError) as e:
+        qmc.qmc_generate_sobol(big, 0, 10)
+    assert e.value.status == 2

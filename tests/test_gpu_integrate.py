@@ -1,0 +1,338 @@
+"""GPU parity of per-pixel integration, the plain path, the adjoint and progressive passes.
+
+Tolerances (derived in the design notes from the FP32 arithmetic of the kernels):
+  estimates: |I32 - I64| <= 2e-5 * max(|I64|, env_p, 1e-6 * max_q env_q), where env_p is the
+             FP64 mean of the envelope |f| bound (Genz: the Gaussian factor; lobes: f itself);
+  gradient vs the oracle's analytic FP64 gradient: |g - g64| <= 1e-4 * max(|g64|, 1e-3 max|g64|);
+  gradient vs central finite differences of the FP64 loss: 1e-3 in the same form.
+Integer samples are compared bit for bit.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import digital, estimator
+from synth import (counts_pow2, counts_uniform, cp_shifts, genz_params, lattice_vector, lobe_params, perturb, pick,
+                   sobol_direction_init)
+
+pytestmark = pytest.mark.gpu
+
+NUS, SHIFT, XOR, BACK = 4, 8, 1, 2
+
+
+def _est_tol(got, ref):
+    env = np.maximum(np.abs(ref["mean"]), ref["env"])
+    floor = 1e-6 * max(float(np.max(ref["env"])), 1e-300)
+    return np.abs(got.astype(np.float64) - ref["mean"]) <= 2e-5 * np.maximum(env, floor)
+
+
+def _mats(s):
+    return digital.sobol_matrices(s, sobol_direction_init(s, 0))
+
+
+def _sampler_pair(q, kind, s, seed, flags):
+    if kind == "sobol":
+        m = _mats(s)
+        return q.PixelSampler.sobol(q.from_u32(m), seed, flags), {"kind": "sobol", "s": s, "table": m,
+                                                                  "seed": seed, "flags": flags}
+    g = lattice_vector(s, 30, 3)
+    return q.PixelSampler.lattice(q.from_u32(g), seed, flags), {"kind": "lattice", "s": s, "table": g,
+                                                                "seed": seed, "flags": flags}
+
+
+def _counts_edge(P):
+    base = np.array([0, 1, 2, 3, 63, 64, 65, 127, 128, 129, 200, 256, 5, 31, 32, 33, 1000], dtype=np.uint32)
+    return np.resize(base, P)
+
+
+def _run_genz(q, sampler, W, H, counts, pp, begin=0, end=2**32 - 1, sums=None):
+    import torch
+
+    ig = q.PixelIntegrand.genz(torch.from_numpy(pp).cuda())
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    means = q.qmc_integrate_pixels(sampler, ig, W, H, dc, begin, end, sums=sums,
+                                   means=torch.empty(W * H, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    return means.cpu().numpy()
+
+
+GENZ_CASES = [
+    # kind, flags, W, H, counts, begin, end
+    ("sobol", NUS | SHIFT, 48, 20, "pow2", 0, 2**32 - 1),
+    ("sobol", NUS | SHIFT | XOR, 37, 11, "edge", 0, 2**32 - 1),     # ragged last tile, all size classes
+    ("sobol", 0, 40, 8, "edge", 0, 2**32 - 1),                      # unscrambled
+    ("sobol", SHIFT, 40, 8, "edge", 64, 200),                       # window, aligned start
+    ("sobol", NUS, 40, 8, "edge", 37, 150),                         # window, unaligned start (general path)
+    ("lattice", SHIFT, 48, 20, "pow2", 0, 2**32 - 1),
+    ("lattice", SHIFT | BACK | XOR, 37, 11, "edge", 0, 2**32 - 1),
+]
+
+
+@pytest.mark.parametrize("case", GENZ_CASES, ids=[f"{c[0]}-{c[1]}-{c[4]}-{c[5]}" for c in GENZ_CASES])
+def test_genz_matches_fp64_oracle(qmc, case):
+    kind, flags, W, H, cname, begin, end = case
+    P = W * H
+    counts = counts_pow2(W, H, 5) if cname == "pow2" else _counts_edge(P)
+    pp = genz_params(P, 4)
+    ds, os_ = _sampler_pair(qmc, kind, 8, 0x1234, flags)
+    got = _run_genz(qmc, ds, W, H, counts, pp, begin, end)
+    ref = estimator.integrate_pixels(os_, {"kind": "genz", "d": 8, "pixel_params": pp}, counts, range(P), begin, end)
+    # a window's mean is (window sum) / N_p
+    ok = _est_tol(got, ref)
+    assert ok.all(), (np.nonzero(~ok)[0][:10], got[~ok][:5], ref["mean"][~ok][:5])
+
+
+def _lobes_setup(q, L, d, seed=6):
+    import torch
+
+    theta = lobe_params(L, d, seed)
+    return theta, torch.from_numpy(theta).cuda()
+
+
+LOBE_CASES = [
+    # d, L, spp/counts, W, H, kind, flags
+    (8, 64, "64", 32, 24, "sobol", NUS | SHIFT),
+    (8, 64, "edge", 37, 5, "sobol", NUS | SHIFT),
+    (8, 3, "edge", 20, 7, "lattice", SHIFT),
+    (5, 70, "edge", 21, 4, "sobol", NUS | SHIFT),          # d < 8, more lobes than one group
+    (64, 32, "64", 8, 4, "sobol", NUS | SHIFT),            # two 32-dim halves per lobe
+    (20, 7, "edge", 9, 3, "lattice", SHIFT | BACK),
+]
+
+
+@pytest.mark.parametrize("case", LOBE_CASES, ids=[f"d{c[0]}-L{c[1]}-{c[2]}-{c[5]}" for c in LOBE_CASES])
+def test_lobes_forward_matches_fp64_oracle(qmc, case):
+    import torch
+
+    d, L, cname, W, H, kind, flags = case
+    P = W * H
+    counts = counts_uniform(W, H, 64) if cname == "64" else _counts_edge(P)
+    theta, dtheta = _lobes_setup(qmc, L, d)
+    ds, os_ = _sampler_pair(qmc, kind, max(d, 8), 77, flags)
+    ig = qmc.PixelIntegrand.lobes(dtheta, L, d, 5)
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    got = qmc.qmc_integrate_pixels(ds, ig, W, H, dc).cpu().numpy()
+    ref = estimator.integrate_pixels(os_, {"kind": "lobes", "d": d, "num_lobes": L, "params": theta,
+                                           "pixel_seed": 5}, counts, range(P))
+    ok = _est_tol(got, ref)
+    assert ok.all(), (np.nonzero(~ok)[0][:10], got[~ok][:5], ref["mean"][~ok][:5])
+
+
+@pytest.mark.parametrize("kind,flags", [("sobol", NUS | SHIFT), ("lattice", SHIFT | BACK)])
+def test_materialised_samples_bit_exact_and_plain_equals_fused(qmc, kind, flags):
+    import torch
+
+    W, H, d = 29, 7, 8
+    P = W * H
+    counts = _counts_edge(P)
+    ds, os_ = _sampler_pair(qmc, kind, 8, 99, flags)
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    offs = qmc.qmc_sample_offsets(dc)
+    torch.cuda.synchronize()
+    want_off = np.concatenate([[0], np.cumsum(counts.astype(np.int64))])
+    assert np.array_equal(offs.cpu().numpy(), want_off)
+    total = int(want_off[-1])
+    pts = qmc.qmc_generate_pixel_samples(ds, d, W, H, dc, offs, total)
+    torch.cuda.synchronize()
+    p_arr = np.repeat(np.arange(P), counts.astype(np.int64))
+    i_arr = np.concatenate([np.arange(c) for c in counts.astype(np.int64)])
+    want = estimator.pixel_samples_f32(os_, p_arr, i_arr)
+    assert np.array_equal(pts.cpu().numpy().view(np.uint32), want.view(np.uint32))
+    # the plain path (integrate the materialised samples) gives bitwise the fused result
+    pp = genz_params(P, 4)
+    fused = _run_genz(qmc, ds, W, H, counts, pp)
+    plain = _run_genz(qmc, qmc.PixelSampler.points(pts, offs), W, H, counts, pp)
+    assert np.array_equal(fused.view(np.uint32), plain.view(np.uint32))
+
+
+def test_sums_accumulate_and_windows_compose(qmc):
+    import torch
+
+    W, H = 16, 8
+    P = W * H
+    counts = _counts_edge(P)
+    pp = genz_params(P, 4)
+    ds, os_ = _sampler_pair(qmc, "sobol", 8, 3, NUS | SHIFT)
+    sums = torch.zeros(P, dtype=torch.float32, device="cuda")
+    for lo, hi in ((0, 64), (64, 128), (128, 2**32 - 1)):
+        _run_genz(qmc, ds, W, H, counts, pp, lo, hi, sums=sums)
+    ref = estimator.integrate_pixels(os_, {"kind": "genz", "d": 8, "pixel_params": pp}, counts, range(P))
+    got = sums.cpu().numpy().astype(np.float64) / np.maximum(counts, 1)
+    assert _est_tol(got.astype(np.float32), ref).all()
+
+
+def test_forward_is_deterministic_across_schedules(qmc):
+    import torch
+
+    W, H = 64, 16
+    P = W * H
+    counts = counts_pow2(W, H, 5)
+    pp = genz_params(P, 4)
+    ds, _ = _sampler_pair(qmc, "sobol", 8, 5, NUS | SHIFT)
+    a = _run_genz(qmc, ds, W, H, counts, pp)
+    b = _run_genz(qmc, ds, W, H, counts, pp)
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    qmc.qmc_autotune_integrate(ds, qmc.PixelIntegrand.genz(torch.from_numpy(pp).cuda()), W, H, dc)
+    c = _run_genz(qmc, ds, W, H, counts, pp)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert np.array_equal(a.view(np.uint32), c.view(np.uint32))
+
+
+def _grad_case(qmc, d, L, W, H, counts, kind="sobol", flags=NUS | SHIFT):
+    import torch
+
+    P = W * H
+    theta, dtheta = _lobes_setup(qmc, L, d)
+    target_theta = perturb(theta, 7)
+    ds, os_ = _sampler_pair(qmc, kind, max(d, 8), 21, flags)
+    ig = qmc.PixelIntegrand.lobes(dtheta, L, d, 9)
+    oig = {"kind": "lobes", "d": d, "num_lobes": L, "params": theta, "pixel_seed": 9}
+    target = estimator.integrate_pixels(os_, dict(oig, params=target_theta), counts, range(P))["mean"]
+    loss, g64, means = estimator.loss_and_gradient(os_, oig, counts, range(P), target)
+    gm = (2.0 * (means - target) / P).astype(np.float32)
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    g = qmc.qmc_integrate_pixels_backward(ds, ig, W, H, dc, torch.from_numpy(gm).cuda())
+    torch.cuda.synchronize()
+    return g.cpu().numpy().astype(np.float64), g64, (os_, oig, counts, target)
+
+
+@pytest.mark.parametrize("d,L,W,H,cname", [(8, 64, 24, 16, "64"), (8, 64, 23, 5, "edge"), (5, 70, 13, 4, "edge"),
+                                           (64, 32, 6, 4, "64"), (20, 7, 9, 3, "edge")])
+def test_adjoint_matches_analytic_fp64_gradient(qmc, d, L, W, H, cname):
+    counts = counts_uniform(W, H, 64) if cname == "64" else _counts_edge(W * H)
+    g, g64, _ = _grad_case(qmc, d, L, W, H, counts)
+    scale = np.max(np.abs(g64))
+    err = np.abs(g - g64)
+    ok = err <= 1e-4 * np.maximum(np.abs(g64), 1e-3 * scale)
+    assert ok.all(), (np.nonzero(~ok)[0][:10], g[~ok][:5], g64[~ok][:5])
+
+
+def test_adjoint_matches_central_differences(qmc):
+    W, H, d, L = 16, 12, 8, 64
+    counts = counts_uniform(W, H, 64)
+    g, g64, (os_, oig, counts, target) = _grad_case(qmc, d, L, W, H, counts)
+    idx = pick(L * (2 * d + 1), 16, 8)
+    fd = estimator.finite_difference(os_, oig, counts, range(W * H), target, idx)
+    scale = np.max(np.abs(fd))
+    ok = np.abs(g[idx] - fd) <= 1e-3 * np.maximum(np.abs(fd), 1e-3 * scale)
+    assert ok.all(), (idx[~ok], g[idx][~ok], fd[~ok])
+
+
+def test_adjoint_is_deterministic(qmc):
+    W, H = 32, 8
+    counts = _counts_edge(W * H)
+    g1, _, _ = _grad_case(qmc, 8, 64, W, H, counts)
+    g2, _, _ = _grad_case(qmc, 8, 64, W, H, counts)
+    assert np.array_equal(g1, g2)
+
+
+def test_autograd_function(qmc):
+    import torch
+
+    W, H, d, L = 16, 8, 8, 16
+    P = W * H
+    counts = counts_uniform(W, H, 64)
+    theta, dtheta = _lobes_setup(qmc, L, d)
+    ds, _ = _sampler_pair(qmc, "sobol", 8, 21, NUS | SHIFT)
+    ig = qmc.PixelIntegrand.lobes(dtheta, L, d, 9)
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    th = dtheta.clone().requires_grad_(True)
+    target = torch.rand(P, device="cuda")
+    means = qmc.integrate(th, ds, ig, W, H, dc)
+    loss = ((means - target) ** 2).mean()
+    loss.backward()
+    gm = (2.0 * (means.detach() - target) / P).contiguous()
+    direct = qmc.qmc_integrate_pixels_backward(ds, ig, W, H, dc, gm)
+    torch.cuda.synchronize()
+    assert torch.equal(th.grad, direct)
+
+
+def test_progressive_graph_replays_match_eager(qmc):
+    import torch
+
+    from synth import counts_progressive
+
+    W, H, d, L = 24, 8, 8, 8
+    P = W * H
+    counts = counts_progressive(W, H, 5, passes=4, spp_per_pass=64)
+    theta, dtheta = _lobes_setup(qmc, L, d)
+    ds, os_ = _sampler_pair(qmc, "sobol", 8, 31, NUS | SHIFT)
+    ig = qmc.PixelIntegrand.lobes(dtheta, L, d, 2)
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    eager = torch.zeros(P, dtype=torch.float32, device="cuda")
+    qmc.qmc_integrate_progressive(ds, ig, W, H, dc, 4, 64, eager, use_graph=False)
+    torch.cuda.synchronize()
+    e = eager.cpu().numpy()
+    for rep in range(3):  # replays of one cached graph, with eager work in between
+        sums = torch.zeros(P, dtype=torch.float32, device="cuda")
+        means = torch.zeros(P, dtype=torch.float32, device="cuda")
+        qmc.qmc_integrate_progressive(ds, ig, W, H, dc, 4, 64, sums, means, use_graph=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(sums.cpu().numpy().view(np.uint32), e.view(np.uint32)), rep
+        torch.zeros(1 << 20, device="cuda").add_(1.0)
+    ref = estimator.integrate_pixels(os_, {"kind": "lobes", "d": d, "num_lobes": L, "params": theta,
+                                           "pixel_seed": 2}, counts, range(P))
+    assert _est_tol(means.cpu().numpy(), ref).all()
+
+
+def test_full_size_genz_sampled_pixels(qmc):
+    """1920x1080, counts 2^k in [1,256], one persistent launch; 1500 sampled pixels vs FP64."""
+    import torch
+
+    W, H = 1920, 1080
+    P = W * H
+    counts = counts_pow2(W, H, 5)
+    pp = genz_params(P, 4)
+    ds, os_ = _sampler_pair(qmc, "sobol", 8, 0xC3, NUS | SHIFT)
+    got = _run_genz(qmc, ds, W, H, counts, pp)
+    pix = pick(P, 1500, 41)
+    ref = estimator.integrate_pixels(os_, {"kind": "genz", "d": 8, "pixel_params": pp}, counts, pix)
+    ok = _est_tol(got[pix], ref)
+    assert ok.all(), (pix[~ok][:10], got[pix][~ok][:5], ref["mean"][~ok][:5])
+
+
+def test_full_size_lobes_forward_sampled_pixels(qmc):
+    """1920x1080 x 64 spp, 64 lobes in 8 dims; 400 sampled pixels vs FP64."""
+    import torch
+
+    W, H, d, L = 1920, 1080, 8, 64
+    P = W * H
+    counts = counts_uniform(W, H, 64)
+    theta, dtheta = _lobes_setup(qmc, L, d)
+    ds, os_ = _sampler_pair(qmc, "sobol", 8, 0xC4, NUS | SHIFT)
+    ig = qmc.PixelIntegrand.lobes(dtheta, L, d, 9)
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    got = qmc.qmc_integrate_pixels(ds, ig, W, H, dc).cpu().numpy()
+    pix = pick(P, 400, 42)
+    ref = estimator.integrate_pixels(os_, {"kind": "lobes", "d": d, "num_lobes": L, "params": theta,
+                                           "pixel_seed": 9}, counts, pix)
+    assert _est_tol(got[pix], ref).all()
+
+
+def test_integration_argument_errors(qmc):
+    import torch
+
+    W, H = 8, 8
+    dc = torch.ones(W * H, dtype=torch.int32, device="cuda")
+    ds, _ = _sampler_pair(qmc, "sobol", 8, 1, NUS | SHIFT)
+    ig = qmc.PixelIntegrand.genz(torch.zeros((W * H, 16), device="cuda"))
+    with pytest.raises(qmc.QMCError) as e:
+        qmc.qmc_integrate_pixels(ds, ig, W, H, dc, 10, 5)
+    assert e.value.status == 1
+    with pytest.raises(qmc.QMCError) as e:
+        qmc.qmc_integrate_pixels_backward(ds, ig, W, H, dc, torch.zeros(W * H, device="cuda"),
+                                          torch.zeros(16, device="cuda"))
+    assert e.value.status == 3
+    small, _ = _sampler_pair(qmc, "sobol", 4, 1, NUS)
+    with pytest.raises(qmc.QMCError) as e:
+        qmc.qmc_integrate_pixels(small, ig, W, H, dc)
+    assert e.value.status == 1
+    lat, _ = _sampler_pair(qmc, "lattice", 8, 1, SHIFT)
+    bad = qmc.PixelSampler(qmc.QMC_SAMPLER_LATTICE, lat.table, 1, NUS)
+    with pytest.raises(qmc.QMCError) as e:
+        qmc.qmc_integrate_pixels(bad, ig, W, H, dc)
+    assert e.value.status == 1
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(qmc.QMCError) as e:
+        qmc.qmc_integrate_pixels(ds, ig, W, H, dc, workspace=ws)
+    assert e.value.status == 5
