@@ -1,12 +1,21 @@
 """Benchmark of the QMC sampling hot path on one MI355X.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extra]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-pixels] [--progressive]
 
 One step = the scrambled-generation workload: 2^24 points x 32 dims of the Sobol'-type
 digital sequence with nested uniform scrambling and an integer Cranley-Patterson rotation,
 written as u32 and float32 (4.29 GB), plus the rank-1 lattice sequence n = 2^20, s = 32
 with a rotation (268 MB).  Inputs (matrices, seeds, generator vector) are resident on the
 GPU before timing starts.  Prints one JSON line.
+
+The same line carries the per-pixel integration workloads ("pixels"): the fused kernels
+(generate + evaluate + reduce in one launch, and the adjoint that recomputes samples) timed
+next to the plain path (materialise the per-pixel samples in HBM, then integrate them):
+  * Genz, 1920x1080 pixels, 2^k samples per pixel (k in 0..8 from a smooth map), d = 8;
+  * Gaussian lobes, 1920x1080 x 64 spp, d = 8, 64 lobes: forward + L2-loss gradient +
+    adjoint ("fwd+bwd").
+With --progressive also the 3840x2160 run: 16 graph-captured passes of 64 spp, d = 64,
+32 lobes, per-pixel counts in [64, 1024], Sobol' and lattice samplers.
 """
 
 import argparse
@@ -59,7 +68,7 @@ def _cpu_job(args):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(points=1 << 21, chunks=64):
+def cpu_baseline(points=1 << 23, chunks=128):
     """The oracle on a bounded sample of the same workload (first `points` indices, 32 dims)."""
     import multiprocessing as mp
 
@@ -78,12 +87,217 @@ def cpu_baseline(points=1 << 21, chunks=64):
                       "processes" % (points, wall, cores)}
 
 
+def _timed(torch, fn, reps, warmup=1):
+    """Mean wall ms of fn over reps (synchronised before and after)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def fill_bandwidth(torch, nbytes=4 << 30, reps=10):
+    """Achievable store-only bandwidth (GB/s) of a plain fill of nbytes."""
+    buf = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    ms = _timed(torch, lambda: buf.fill_(1.0), reps, 2)
+    del buf
+    return nbytes / (ms * 1e-3) / 1e9
+
+
+def pixel_workloads(torch, q, reps, progressive):
+    """Fused vs plain per-pixel integration (see the module docstring)."""
+    import numpy as np
+
+    from synth import counts_pow2, counts_progressive, counts_uniform, genz_params, lattice_vector, lobe_params
+    from synth import sobol_direction_init
+
+    out = {}
+    W, H = 1920, 1080
+    P = W * H
+    m8 = q.from_u32(q.qmc_sobol_matrices(8, sobol_direction_init(8, 0)))
+    sp = q.PixelSampler.sobol(m8, 0xC3)
+
+    # Genz, uneven power-of-two counts
+    c3 = counts_pow2(W, H, 5)
+    n3 = int(c3.astype(np.int64).sum())
+    dc3 = torch.from_numpy(c3.view(np.int32)).cuda()
+    ig3 = q.PixelIntegrand.genz(torch.from_numpy(genz_params(P, 4)).cuda())
+    q.qmc_autotune_integrate(sp, ig3, W, H, dc3)
+    ws3 = torch.empty(max(q.qmc_workspace_size(sp, ig3, W, H), 256), dtype=torch.uint8, device="cuda")
+    means = torch.empty(P, dtype=torch.float32, device="cuda")
+    fused3 = _timed(torch, lambda: q.qmc_integrate_pixels(sp, ig3, W, H, dc3, means=means, workspace=ws3), reps)
+    off3 = q.qmc_sample_offsets(dc3)
+    pts3 = torch.empty((8, n3), dtype=torch.float32, device="cuda")
+    ptsamp3 = q.PixelSampler.points(pts3, off3)
+
+    def plain3():
+        q.qmc_generate_pixel_samples(sp, 8, W, H, dc3, off3, n3, out=pts3)
+        q.qmc_integrate_pixels(ptsamp3, ig3, W, H, dc3, means=means, workspace=ws3)
+
+    plain_ms3 = _timed(torch, plain3, reps)
+    out["genz_1920x1080_uneven"] = {
+        "pixel_samples": n3, "fused_ms": round(fused3, 4), "plain_ms": round(plain_ms3, 4),
+        "fused_pixel_samples_per_s": round(n3 / (fused3 * 1e-3), 1),
+        "plain_pixel_samples_per_s": round(n3 / (plain_ms3 * 1e-3), 1),
+        "speedup_vs_plain": round(plain_ms3 / fused3, 3)}
+    del pts3
+
+    # Gaussian lobes, forward + L2 gradient + adjoint
+    L, d = 64, 8
+    c4 = counts_uniform(W, H, 64)
+    n4 = P * 64
+    dc4 = torch.from_numpy(c4.view(np.int32)).cuda()
+    theta = torch.from_numpy(lobe_params(L, d, 6)).cuda()
+    ig4 = q.PixelIntegrand.lobes(theta, L, d, 9)
+    target = torch.rand(P, device="cuda")
+    gm = torch.empty(P, dtype=torch.float32, device="cuda")
+    q.qmc_autotune_integrate(sp, ig4, W, H, dc4)
+    q.qmc_autotune_integrate(sp, ig4, W, H, dc4, backward=True, grad_means=gm.fill_(1e-7))
+    wsf = torch.empty(max(q.qmc_workspace_size(sp, ig4, W, H, False), 256), dtype=torch.uint8, device="cuda")
+    wsb = torch.empty(q.qmc_workspace_size(sp, ig4, W, H, True), dtype=torch.uint8, device="cuda")
+    grad = torch.zeros(theta.numel(), dtype=torch.float32, device="cuda")
+
+    def fwd_bwd(sampler):
+        q.qmc_integrate_pixels(sampler, ig4, W, H, dc4, means=means, workspace=wsf)
+        torch.sub(means, target, out=gm).mul_(2.0 / P)
+        grad.zero_()
+        q.qmc_integrate_pixels_backward(sampler, ig4, W, H, dc4, gm, grad, workspace=wsb)
+
+    wss = torch.empty(q.qmc_workspace_size(sp, ig4, W, H, 2), dtype=torch.uint8, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+
+    def step(sampler):
+        loss.zero_()
+        grad.zero_()
+        q.qmc_integrate_pixels_l2_step(sampler, ig4, W, H, dc4, target, means, loss, grad, workspace=wss)
+
+    fwd_only = _timed(torch, lambda: q.qmc_integrate_pixels(sp, ig4, W, H, dc4, means=means, workspace=wsf), reps)
+    two_kernel = _timed(torch, lambda: fwd_bwd(sp), reps)
+    fused4 = _timed(torch, lambda: step(sp), reps)
+    off4 = q.qmc_sample_offsets(dc4)
+    pts4 = torch.empty((d, n4), dtype=torch.float32, device="cuda")
+    ptsamp4 = q.PixelSampler.points(pts4, off4)
+
+    def plain4():
+        q.qmc_generate_pixel_samples(sp, d, W, H, dc4, off4, n4, out=pts4)
+        fwd_bwd(ptsamp4)
+
+    def plain_step():
+        q.qmc_generate_pixel_samples(sp, d, W, H, dc4, off4, n4, out=pts4)
+        step(ptsamp4)
+
+    plain_ms4 = _timed(torch, plain4, reps)
+    plain_step_ms = _timed(torch, plain_step, reps)
+    out["lobes_1920x1080x64_fwd_bwd"] = {
+        "pixel_samples": n4, "lobes": L, "dims": d, "params": theta.numel(),
+        "fused_fwd_ms": round(fwd_only, 4),
+        "fused_fwd_bwd_ms": round(fused4, 4),
+        "fused_fwd_then_bwd_two_kernels_ms": round(two_kernel, 4),
+        "plain_fwd_bwd_ms": round(plain_step_ms, 4),
+        "plain_fwd_then_bwd_two_kernels_ms": round(plain_ms4, 4),
+        "fused_fwd_bwd_pixel_samples_per_s": round(n4 / (fused4 * 1e-3), 1),
+        "plain_fwd_bwd_pixel_samples_per_s": round(n4 / (plain_step_ms * 1e-3), 1),
+        "speedup_vs_plain": round(plain_step_ms / fused4, 3),
+        "note": "fused: one kernel samples each pixel once and forms the estimate, the L2 loss gradient and the "
+                "adjoint; plain: the samples are materialised in HBM first and the same kernel reads them"}
+    del pts4
+
+    if progressive:
+        W5, H5, L5, d5 = 3840, 2160, 32, 64
+        P5 = W5 * H5
+        c5 = counts_progressive(W5, H5, 5, passes=16, spp_per_pass=64)
+        n5 = int(c5.astype(np.int64).sum())
+        dc5 = torch.from_numpy(c5.view(np.int32)).cuda()
+        th5 = torch.from_numpy(lobe_params(L5, d5, 6)).cuda()
+        ig5 = q.PixelIntegrand.lobes(th5, L5, d5, 9)
+        m64 = q.from_u32(q.qmc_sobol_matrices(64, sobol_direction_init(64, 0)))
+        samplers = {"sobol": q.PixelSampler.sobol(m64, 0xC5),
+                    "lattice": q.PixelSampler.lattice(q.from_u32(lattice_vector(64, 30, 3)), 0xC5)}
+        sums = torch.zeros(P5, dtype=torch.float32, device="cuda")
+        means5 = torch.empty(P5, dtype=torch.float32, device="cuda")
+        ws5 = torch.empty(max(q.qmc_workspace_size(samplers["sobol"], ig5, W5, H5), 256), dtype=torch.uint8,
+                          device="cuda")
+        rec = {"pixel_samples": n5, "passes": 16, "spp_per_pass": 64, "dims": d5, "lobes": L5}
+        for name, smp in samplers.items():
+            def run(graph):
+                sums.zero_()
+                q.qmc_integrate_progressive(smp, ig5, W5, H5, dc5, 16, 64, sums, means5, ws5, use_graph=graph)
+            g_ms = _timed(torch, lambda: run(True), 1)
+            e_ms = _timed(torch, lambda: run(False), 1)
+            rec[name] = {"graph_ms": round(g_ms, 3), "eager_ms": round(e_ms, 3),
+                         "pixel_samples_per_s": round(n5 / (g_ms * 1e-3), 1)}
+        gm5 = torch.full((P5,), 1e-8, dtype=torch.float32, device="cuda")
+        g5 = torch.zeros(th5.numel(), dtype=torch.float32, device="cuda")
+        wsb5 = torch.empty(q.qmc_workspace_size(samplers["sobol"], ig5, W5, H5, True), dtype=torch.uint8,
+                           device="cuda")
+        b_ms = _timed(torch, lambda: q.qmc_integrate_pixels_backward(samplers["sobol"], ig5, W5, H5, dc5, gm5, g5,
+                                                                     workspace=wsb5), 1)
+        rec["sobol"]["backward_ms"] = round(b_ms, 3)
+        out["progressive_3840x2160_d64"] = rec
+    return out
+
+
+def pmc_probe(torch, q):
+    """A copy of exactly 1 GiB (reads 1 GiB, writes 1 GiB) followed by one scrambled-Sobol'
+    generation launch of the benchmark workload; each kernel runs once."""
+    from synth import cp_shifts, nus_seeds, sobol_direction_init
+
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    s, n = 32, 1 << 24
+    mats = q.from_u32(q.qmc_sobol_matrices(s, sobol_direction_init(s, 0)))
+    seeds = q.from_u32(nus_seeds(s, 1))
+    shifts = q.from_u32(cp_shifts(s, 2))
+    su = torch.empty((s, n), dtype=torch.int32, device="cuda")
+    sf = torch.empty((s, n), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    q.qmc_generate_sobol(mats, 0, n, seeds, shifts, 0, out_u32=su, out_f32=sf)
+    torch.cuda.synchronize()
+    print("pmc probe done", flush=True)
+
+
+def pmc_probe_pixels(torch, q):
+    """One launch each of the fused pixel kernels on the benchmark workloads (default launch
+    shapes), for VALU counter runs."""
+    import numpy as np
+
+    from synth import counts_pow2, counts_uniform, genz_params, lobe_params, sobol_direction_init
+
+    W, H = 1920, 1080
+    P = W * H
+    sp = q.PixelSampler.sobol(q.from_u32(q.qmc_sobol_matrices(8, sobol_direction_init(8, 0))), 0xC3)
+    dc3 = torch.from_numpy(counts_pow2(W, H, 5).view(np.int32)).cuda()
+    ig3 = q.PixelIntegrand.genz(torch.from_numpy(genz_params(P, 4)).cuda())
+    dc4 = torch.from_numpy(counts_uniform(W, H, 64).view(np.int32)).cuda()
+    ig4 = q.PixelIntegrand.lobes(torch.from_numpy(lobe_params(64, 8, 6)).cuda(), 64, 8, 9)
+    gm = torch.full((P,), 1e-7, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    q.qmc_integrate_pixels(sp, ig3, W, H, dc3)
+    torch.cuda.synchronize()
+    q.qmc_integrate_pixels(sp, ig4, W, H, dc4)
+    torch.cuda.synchronize()
+    q.qmc_integrate_pixels_backward(sp, ig4, W, H, dc4, gm)
+    torch.cuda.synchronize()
+    print("pmc pixel probe done", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-pixels", action="store_true", help="skip the per-pixel integration workloads")
+    ap.add_argument("--progressive", action="store_true", help="also run the 3840x2160 progressive workload")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="for counter runs: one 1 GiB copy (calibration), then one generation launch; no JSON")
+    ap.add_argument("--pmc-probe-pixels", action="store_true",
+                    help="for counter runs: one launch each of the fused Genz, lobe forward and lobe adjoint kernels")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)"
@@ -97,6 +311,13 @@ def main():
     from synth import cp_shifts, lattice_vector, nus_seeds, sobol_direction_init
 
     torch.cuda.set_device(0)
+    if args.pmc_probe:
+        pmc_probe(torch, q)
+        return
+    if args.pmc_probe_pixels:
+        pmc_probe_pixels(torch, q)
+        return
+    fill_gbs = fill_bandwidth(torch)
     s, n = 32, 1 << 24
     nl = 1 << 20
     mats = q.from_u32(q.qmc_sobol_matrices(s, sobol_direction_init(s, 0)))
@@ -154,8 +375,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "sobol_fast (scramble + rotation, u32 + f32)",
-                     "kernel_ms": round(sobol_ms, 4), "algorithmic_bytes": alg_bytes},
+                     "kernel_ms": round(sobol_ms, 4), "algorithmic_bytes": alg_bytes,
+                     "fill_gbs": round(fill_gbs, 1), "frac_of_fill": round(achieved / fill_gbs, 4)},
     }
+    del su, sf, lu, lf
+    torch.cuda.empty_cache()
+    if not args.no_pixels:
+        out["pixels"] = pixel_workloads(torch, q, max(3, args.steps // 4), args.progressive)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

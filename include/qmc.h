@@ -195,9 +195,10 @@ typedef struct {
     const float* pixel_params; /* GENZ: device [P][16]                                           */
 } qmc_integrand;
 
-/* Bytes of device workspace needed by qmc_integrate_pixels (backward = 0) or by
- * qmc_integrate_pixels_backward (backward = 1) for this problem, in *bytes.  The workspace
- * holds a work counter and, for the backward pass, per-wavefront gradient partials.
+/* Bytes of device workspace needed by qmc_integrate_pixels (backward = 0), by
+ * qmc_integrate_pixels_backward (backward = 1) or by qmc_integrate_pixels_l2_step
+ * (backward = 2) for this problem, in *bytes.  The workspace holds a work counter and, for
+ * the adjoint, per-task partial gradients and their FP64 chunk sums.
  * Errors: INVALID_ARGUMENT (NULL), UNSUPPORTED (kind/dimension combination). */
 qmc_status qmc_workspace_size(qmc_context ctx, const qmc_sampler* sampler, const qmc_integrand* integrand,
                               uint32_t width, uint32_t height, int backward, size_t* bytes);
@@ -227,6 +228,23 @@ qmc_status qmc_integrate_pixels_backward(qmc_context ctx, qmc_stream stream, con
                                          const uint32_t* counts, uint32_t sample_begin, uint32_t sample_end,
                                          const float* grad_means, float* grad_params, void* workspace,
                                          size_t workspace_bytes);
+
+/* One fused training step for the per-pixel L2 loss L = (1/P) sum_p (I_p - T_p)^2 of the
+ * lobe integrand over the full windows [0, N_p): estimates I_p, dL/dI_p = 2 (I_p - T_p) / P
+ * and the adjoint of qmc_integrate_pixels_backward, in one launch (plus the fixed-order FP64
+ * reduction).  The adjoint's per-pixel sums do not depend on dL/dI_p, only their scaling
+ * does, so with at most 64 lobes (32 when d > 32) one pass over each pixel's samples
+ * accumulates the estimate and the unscaled adjoint sums together and scales them when the
+ * pixel is complete: samples are generated once.  With more lobes the forward pass over all
+ * lobes precedes the adjoint pass (samples are generated again).
+ *   target: device float32 [P];  means: device float32 [P] or NULL (written);
+ *   loss: device float32 [1], L is added;  grad_params: device float32 [L*(2d+1)], added.
+ *   workspace: >= qmc_workspace_size(..., 2) bytes.
+ * Errors as for qmc_integrate_pixels_backward. */
+qmc_status qmc_integrate_pixels_l2_step(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
+                                        const qmc_integrand* integrand, uint32_t width, uint32_t height,
+                                        const uint32_t* counts, const float* target, float* means, float* loss,
+                                        float* grad_params, void* workspace, size_t workspace_bytes);
 
 /* Exclusive prefix sums of counts: offsets[p] = sum_{q<p} counts[q] (device u64 [num_pixels+1],
  * offsets[num_pixels] = total).  workspace: >= 8 * (num_pixels / 1024 + 2) bytes.  Used to lay

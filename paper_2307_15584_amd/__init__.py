@@ -249,9 +249,10 @@ class PixelIntegrand:
 
 
 def qmc_workspace_size(sampler, integrand, width, height, backward=False):
+    """Workspace bytes: backward False/0 forward, True/1 adjoint, 2 fused L2 step."""
     n = ctypes.c_size_t()
     check(load().qmc_workspace_size(context(), ctypes.byref(sampler.c), ctypes.byref(integrand.c), width, height,
-                                    1 if backward else 0, ctypes.byref(n)))
+                                    int(backward), ctypes.byref(n)))
     return n.value
 
 
@@ -304,6 +305,31 @@ def qmc_integrate_pixels_backward(sampler, integrand, width, height, counts, gra
         _dev_ptr(grad_means, "grad_means", (torch.float32,)), _dev_ptr(grad_params, "grad_params", (torch.float32,)),
         _dev_ptr(workspace, "workspace"), workspace.numel()))
     return grad_params
+
+
+def qmc_integrate_pixels_l2_step(sampler, integrand, width, height, counts, target, means=None, loss=None,
+                                 grad_params=None, workspace=None):
+    """Fused forward + L2-loss gradient + adjoint.  Returns (means, loss[1], grad_params);
+    loss and grad_params are added into (zeros when not given)."""
+    torch = _torch()
+    P = width * height
+    _check_counts(counts, P)
+    if target.numel() != P:
+        raise ValueError("target must have width*height entries")
+    if means is None:
+        means = torch.empty(P, dtype=torch.float32, device=counts.device)
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float32, device=counts.device)
+    if grad_params is None:
+        grad_params = torch.zeros(integrand.params.numel(), dtype=torch.float32, device=counts.device)
+    if workspace is None:
+        workspace = _workspace(qmc_workspace_size(sampler, integrand, width, height, 2), counts.device)
+    check(load().qmc_integrate_pixels_l2_step(
+        context(counts.device), _stream(), ctypes.byref(sampler.c), ctypes.byref(integrand.c), width, height,
+        _dev_ptr(counts, "counts", _u32_types()), _dev_ptr(target, "target", (torch.float32,)),
+        _dev_ptr(means, "means", (torch.float32,)), _dev_ptr(loss, "loss", (torch.float32,)),
+        _dev_ptr(grad_params, "grad_params", (torch.float32,)), _dev_ptr(workspace, "workspace"), workspace.numel()))
+    return means, loss, grad_params
 
 
 def qmc_sample_offsets(counts):

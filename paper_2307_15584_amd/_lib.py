@@ -69,6 +69,8 @@ SIGNATURES = {
                                    ctypes.c_size_t]),
     "qmc_integrate_pixels_backward": (_st, [_vp, _vp, _vp, _vp, _u32, _u32, _vp, _u32, _u32, _vp, _vp, _vp,
                                             ctypes.c_size_t]),
+    "qmc_integrate_pixels_l2_step": (_st, [_vp, _vp, _vp, _vp, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                           ctypes.c_size_t]),
     "qmc_sample_offsets": (_st, [_vp, _vp, _vp, _u32, _vp, _vp, ctypes.c_size_t]),
     "qmc_generate_pixel_samples": (_st, [_vp, _vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp, _u64, _vp,
                                          ctypes.c_size_t]),

@@ -21,6 +21,18 @@ __device__ __forceinline__ float u32_to_unifloat(uint32_t u) {
     return __builtin_ldexpf(static_cast<float>(m), -static_cast<int>(z) - 24);
 }
 
+// Switches this wavefront's FP32 rounding to round-toward-zero (MODE register, single-precision
+// round field = 3).  The mode is per-wavefront state initialised at wave launch, so it only
+// affects the calling kernel, which must perform no other FP32 arithmetic that relies on
+// round-to-nearest.
+__device__ __forceinline__ void set_fp32_round_toward_zero() { __builtin_amdgcn_s_setreg(0x801, 3); }
+
+// Same result as u32_to_unifloat, valid only after set_fp32_round_toward_zero(): the
+// conversion truncates u to 24 significant bits and the scaling by 2^-32 is exact.
+__device__ __forceinline__ float u32_to_unifloat_rtz(uint32_t u) {
+    return __builtin_amdgcn_ldexpf(static_cast<float>(u), -32);
+}
+
 // The low-to-high mixing P_s of the nested uniform scramble, applied to the mirrored value.
 // sm = (s >> 8) & 0xFFFFFE is the seed-dependent even multiplier, precomputed per seed.
 // __umul24 multiplies the low 24 bits of both operands (every multiplier is below 2^24).

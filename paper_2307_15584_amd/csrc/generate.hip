@@ -12,7 +12,9 @@
 //   * moving a lane from index i to i+256 flips index bits 8..8+t, t = ctz((i>>8)+1), so
 //     x(i+256) = x(i) ^ Q[t] with Q[t] = C[8]^...^C[8+t], a table built once per block.
 // With scrambling the columns are staged bit-reversed, which yields the mirrored value the
-// nested scramble starts from at no cost.
+// nested scramble starts from at no cost.  Every kernel here switches its wavefronts to
+// round-toward-zero FP32 rounding on entry, so the float conversion is the hardware
+// u32 -> f32 conversion (which then truncates) followed by an exact scaling by 2^-32.
 #include "common.hpp"
 #include "device_core.hpp"
 
@@ -57,13 +59,13 @@ __device__ __forceinline__ void emit4(uint32_t* ou, float* of, uint64_t off, uin
         if constexpr (WU) store_vec<NT>(reinterpret_cast<u32x4*>(ou + off), u32x4{r0, r1, r2, r3});
         if constexpr (WF)
             store_vec<NT>(reinterpret_cast<f32x4*>(of + off),
-                          f32x4{dev::u32_to_unifloat(r0), dev::u32_to_unifloat(r1), dev::u32_to_unifloat(r2),
-                                dev::u32_to_unifloat(r3)});
+                          f32x4{dev::u32_to_unifloat_rtz(r0), dev::u32_to_unifloat_rtz(r1), dev::u32_to_unifloat_rtz(r2),
+                                dev::u32_to_unifloat_rtz(r3)});
     } else {
         const uint32_t r[4] = {r0, r1, r2, r3};
         for (uint32_t q = 0; q < valid; ++q) {
             if constexpr (WU) store_one<NT>(ou + off + q, r[q]);
-            if constexpr (WF) store_one<NT>(of + off + q, dev::u32_to_unifloat(r[q]));
+            if constexpr (WF) store_one<NT>(of + off + q, dev::u32_to_unifloat_rtz(r[q]));
         }
     }
 }
@@ -76,10 +78,12 @@ struct SobolLds {
     uint32_t shift[QMC_MAX_DIMS];
 };
 
+// Q[j][t] = XOR of columns q0..q0+t of dimension j: moving an index by 2^q0 flips its bits
+// q0..q0+t with t = ctz((i >> q0) + 1), so the point moves by Q[j][t].
 template <bool NUS, bool SHIFT>
 __device__ __forceinline__ void stage_sobol(SobolLds& L, const uint32_t* __restrict__ mats, uint32_t s,
                                             const uint32_t* __restrict__ seeds, const uint32_t* __restrict__ shifts,
-                                            bool build_q) {
+                                            bool build_q, uint32_t q0 = 8) {
     const uint32_t tid = threadIdx.x;
     for (uint32_t t = tid; t < s * 32; t += blockDim.x) {
         const uint32_t c = mats[t];
@@ -97,7 +101,7 @@ __device__ __forceinline__ void stage_sobol(SobolLds& L, const uint32_t* __restr
         for (uint32_t t = tid; t < s * kQ; t += blockDim.x) {
             const uint32_t j = t / kQ, k = t % kQ;
             uint32_t acc = 0;
-            for (uint32_t b = 0; b <= k; ++b) acc ^= L.cols[j][8 + b];
+            for (uint32_t b = 0; b <= k && q0 + b < 32; ++b) acc ^= L.cols[j][q0 + b];
             L.q[j][k] = acc;
         }
         __syncthreads();
@@ -111,20 +115,30 @@ __device__ __forceinline__ uint32_t matrix_product(const uint32_t* cols, uint32_
     return x;
 }
 
+// Chunk order: wavefront w handles chunks c0 + k * step for k < steps, where
+//   contiguous runs: c0 = w * steps, step = 1;
+//   interleaved:     c0 = w, step = W (all wavefronts, a power of two), so at every step the
+//                    whole grid writes one contiguous window of W chunks per output array.
+// step * 256 = 2^q0 indices, and the Q table is built from column q0.
 template <bool NUS, bool SHIFT, bool SXOR, bool WU, bool WF, bool NT>
 __global__ __launch_bounds__(kBlock) void sobol_fast(const uint32_t* __restrict__ mats, uint32_t s, uint32_t first,
                                                      uint32_t n, const uint32_t* __restrict__ seeds,
                                                      const uint32_t* __restrict__ shifts, uint32_t* __restrict__ ou,
-                                                     float* __restrict__ of, uint64_t ld, uint32_t cpw,
-                                                     uint32_t nchunks) {
+                                                     float* __restrict__ of, uint64_t ld, uint32_t steps,
+                                                     uint32_t nchunks, uint32_t interleaved, uint32_t q0) {
+    dev::set_fp32_round_toward_zero();
     __shared__ SobolLds L;
-    stage_sobol<NUS, SHIFT>(L, mats, s, seeds, shifts, true);
-    const uint32_t wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    stage_sobol<NUS, SHIFT>(L, mats, s, seeds, shifts, true, q0);
+    const uint32_t wave = blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t c0 = wave * cpw;
+    const uint32_t step = interleaved ? gridDim.x * kWavesPerBlock : 1u;
+    const uint32_t c0 = interleaved ? wave : wave * steps;
     if (c0 >= nchunks) return;
-    const uint32_t c1 = min(c0 + cpw, nchunks);
+    const uint32_t kmax = interleaved ? (nchunks - c0 + step - 1) / step : min(steps, nchunks - c0);
+    const uint32_t full = n / kChunk;  // chunks with all 256 indices in range
+    const uint32_t stride = step * kChunk;
     for (uint32_t j = 0; j < s; ++j) {
+        uint32_t c = c0;
         uint32_t o = c0 * kChunk + 4u * lane;
         uint32_t i = first + o;
         uint32_t x = matrix_product(L.cols[j], i);
@@ -132,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void sobol_fast(const uint32_t* __restrict_
         const uint32_t seed = NUS ? L.seed[j] : 0u, sm = NUS ? L.sm[j] : 0u;
         const uint32_t sh = SHIFT ? L.shift[j] : 0u;
         const uint64_t base = uint64_t(j) * ld;
-        for (uint32_t c = c0; c < c1; ++c) {
+        for (uint32_t k = 0; k < kmax; ++k) {
             uint32_t v0 = x, v1 = x ^ col0, v2 = x ^ col1, v3 = x ^ col0 ^ col1;
             if constexpr (NUS) {
                 v0 = dev::nus_from_mirrored(v0, seed, sm);
@@ -140,12 +154,16 @@ __global__ __launch_bounds__(kBlock) void sobol_fast(const uint32_t* __restrict_
                 v2 = dev::nus_from_mirrored(v2, seed, sm);
                 v3 = dev::nus_from_mirrored(v3, seed, sm);
             }
-            if (o < n) emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, min(n - o, 4u), v0, v1, v2, v3, sh);
-            if (c + 1 < c1) {
-                const uint32_t t = min(static_cast<uint32_t>(__builtin_ctz((i >> 8) + 1u)), kQ - 1);
+            if (c < full)
+                emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, 4u, v0, v1, v2, v3, sh);
+            else if (o < n)
+                emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, min(n - o, 4u), v0, v1, v2, v3, sh);
+            if (k + 1 < kmax) {
+                const uint32_t t = min(static_cast<uint32_t>(__builtin_ctz((i >> q0) + 1u)), kQ - 1);
                 x ^= L.q[j][t];
-                i += kChunk;
-                o += kChunk;
+                i += stride;
+                o += stride;
+                c += step;
             }
         }
     }
@@ -157,6 +175,7 @@ __global__ __launch_bounds__(kBlock) void sobol_general(const uint32_t* __restri
                                                         uint32_t n, const uint32_t* __restrict__ seeds,
                                                         const uint32_t* __restrict__ shifts, uint32_t* __restrict__ ou,
                                                         float* __restrict__ of, uint64_t ld) {
+    dev::set_fp32_round_toward_zero();
     __shared__ SobolLds L;
     stage_sobol<NUS, SHIFT>(L, mats, s, seeds, shifts, false);
     for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < n; o += gridDim.x * kBlock) {
@@ -166,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void sobol_general(const uint32_t* __restri
             if constexpr (NUS) v = dev::nus_from_mirrored(v, L.seed[j], L.sm[j]);
             if constexpr (SHIFT) v = dev::apply_shift<SXOR>(v, L.shift[j]);
             if constexpr (WU) ou[uint64_t(j) * ld + o] = v;
-            if constexpr (WF) of[uint64_t(j) * ld + o] = dev::u32_to_unifloat(v);
+            if constexpr (WF) of[uint64_t(j) * ld + o] = dev::u32_to_unifloat_rtz(v);
         }
     }
 }
@@ -193,22 +212,26 @@ template <bool BACK, bool SHIFT, bool SXOR, bool WU, bool WF, bool NT>
 __global__ __launch_bounds__(kBlock) void lattice_fast(const uint32_t* __restrict__ gen, uint32_t s, uint32_t first,
                                                        uint32_t n, const uint32_t* __restrict__ shifts,
                                                        uint32_t* __restrict__ ou, float* __restrict__ of, uint64_t ld,
-                                                       uint32_t cpw, uint32_t nchunks) {
+                                                       uint32_t cpw, uint32_t nchunks, uint32_t interleaved) {
+    dev::set_fp32_round_toward_zero();
     __shared__ LatticeLds L;
     stage_lattice<SHIFT>(L, gen, s, shifts);
-    const uint32_t wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const uint32_t wave = blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t c0 = wave * cpw;
+    const uint32_t step = interleaved ? gridDim.x * kWavesPerBlock : 1u;
+    const uint32_t c0 = interleaved ? wave : wave * cpw;
     if (c0 >= nchunks) return;
-    const uint32_t c1 = min(c0 + cpw, nchunks);
+    const uint32_t kmax = interleaved ? (nchunks - c0 + step - 1) / step : min(cpw, nchunks - c0);
+    const uint32_t full = n / kChunk;
     for (uint32_t j = 0; j < s; ++j) {
         const uint32_t g = L.g[j];
         const uint32_t h1 = g << 31, h2 = g << 30, h3 = h1 + h2;
         const uint32_t sh = SHIFT ? L.shift[j] : 0u;
         const uint64_t base = uint64_t(j) * ld;
-        uint32_t o = c0 * kChunk + 4u * lane;
-        for (uint32_t c = c0; c < c1; ++c, o += kChunk) {
-            if (o >= n) break;
+        for (uint32_t k = 0; k < kmax; ++k) {
+            const uint32_t c = c0 + k * step;
+            const uint32_t o = c * kChunk + 4u * lane;
+            if (c >= full && o >= n) break;
             const uint32_t b = dev::brev(first + o);
             uint32_t v0, v1, v2, v3;
             if constexpr (BACK) {
@@ -222,7 +245,10 @@ __global__ __launch_bounds__(kBlock) void lattice_fast(const uint32_t* __restric
                 v2 = v0 + h2;
                 v3 = v0 + h3;
             }
-            emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, min(n - o, 4u), v0, v1, v2, v3, sh);
+            if (c < full)
+                emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, 4u, v0, v1, v2, v3, sh);
+            else
+                emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, min(n - o, 4u), v0, v1, v2, v3, sh);
         }
     }
 }
@@ -232,6 +258,7 @@ __global__ __launch_bounds__(kBlock) void lattice_general(const uint32_t* __rest
                                                           uint32_t n, const uint32_t* __restrict__ shifts,
                                                           uint32_t* __restrict__ ou, float* __restrict__ of,
                                                           uint64_t ld) {
+    dev::set_fp32_round_toward_zero();
     __shared__ LatticeLds L;
     stage_lattice<SHIFT>(L, gen, s, shifts);
     for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < n; o += gridDim.x * kBlock) {
@@ -241,24 +268,26 @@ __global__ __launch_bounds__(kBlock) void lattice_general(const uint32_t* __rest
             uint32_t v = b * L.g[j];
             if constexpr (SHIFT) v = dev::apply_shift<SXOR>(v, L.shift[j]);
             if constexpr (WU) ou[uint64_t(j) * ld + o] = v;
-            if constexpr (WF) of[uint64_t(j) * ld + o] = dev::u32_to_unifloat(v);
+            if constexpr (WF) of[uint64_t(j) * ld + o] = dev::u32_to_unifloat_rtz(v);
         }
     }
 }
 
 __global__ __launch_bounds__(kBlock) void unifloat_vec(const u32x4* __restrict__ in, f32x4* __restrict__ out,
                                                        uint64_t nvec) {
+    dev::set_fp32_round_toward_zero();
     for (uint64_t k = uint64_t(blockIdx.x) * kBlock + threadIdx.x; k < nvec; k += uint64_t(gridDim.x) * kBlock) {
         const u32x4 u = in[k];
-        out[k] = f32x4{dev::u32_to_unifloat(u.x), dev::u32_to_unifloat(u.y), dev::u32_to_unifloat(u.z),
-                       dev::u32_to_unifloat(u.w)};
+        out[k] = f32x4{dev::u32_to_unifloat_rtz(u.x), dev::u32_to_unifloat_rtz(u.y), dev::u32_to_unifloat_rtz(u.z),
+                       dev::u32_to_unifloat_rtz(u.w)};
     }
 }
 
 __global__ __launch_bounds__(kBlock) void unifloat_scalar(const uint32_t* __restrict__ in, float* __restrict__ out,
                                                           uint64_t begin, uint64_t n) {
+    dev::set_fp32_round_toward_zero();
     for (uint64_t k = begin + uint64_t(blockIdx.x) * kBlock + threadIdx.x; k < n; k += uint64_t(gridDim.x) * kBlock)
-        out[k] = dev::u32_to_unifloat(in[k]);
+        out[k] = dev::u32_to_unifloat_rtz(in[k]);
 }
 
 template <typename F>
@@ -313,10 +342,22 @@ qmc_status validate_generation(const char* who, qmc_context ctx, const void* tab
     return QMC_OK;
 }
 
-uint32_t fast_grid(uint64_t n, uint32_t cpw, uint32_t* nchunks) {
+// Grid of the fast kernels.  Contiguous runs: one wavefront per `cpw` chunks.  Interleaved:
+// a power-of-two number of wavefronts (at most tune.waves, at most one per chunk), so that the
+// index stride between a wavefront's chunks is a power of two.
+uint32_t fast_grid(uint64_t n, const GenTune& tn, uint32_t* nchunks, uint32_t* q0) {
     *nchunks = static_cast<uint32_t>((n + kChunk - 1) / kChunk);
-    const uint32_t waves = (*nchunks + cpw - 1) / cpw;
-    return (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (!tn.interleaved) {
+        *q0 = 8;
+        const uint32_t waves = (*nchunks + tn.chunks_per_wave - 1) / tn.chunks_per_wave;
+        return (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    }
+    uint32_t waves = kWavesPerBlock;
+    while (waves * 2 <= tn.waves && waves * 2 <= *nchunks) waves *= 2;
+    uint32_t lg = 0;
+    while ((1u << lg) < waves) ++lg;
+    *q0 = 8 + lg;
+    return waves / kWavesPerBlock;
 }
 
 uint32_t general_grid(const qmc_context ctx, uint64_t n) {
@@ -359,12 +400,13 @@ extern "C" qmc_status qmc_generate_sobol(qmc_context ctx, qmc_stream stream, con
                 with_outputs(out_u32 != nullptr, out_f32 != nullptr, [&](auto WU, auto WF) {
                     if (fast) {
                         with_bool(ctx->sobol_tune.nontemporal != 0, [&](auto NT) {
-                            uint32_t nchunks;
-                            const uint32_t cpw = ctx->sobol_tune.chunks_per_wave;
-                            const uint32_t grid = fast_grid(nn, cpw, &nchunks);
+                            uint32_t nchunks, q0;
+                            const GenTune& tn = ctx->sobol_tune;
+                            const uint32_t grid = fast_grid(nn, tn, &nchunks, &q0);
                             hipLaunchKernelGGL((sobol_fast<NUS.value, SH.value, SX.value, WU.value, WF.value, NT.value>),
                                                dim3(grid), dim3(kBlock), 0, hs, matrices, s, first32, nn, nus_seeds,
-                                               shifts, out_u32, out_f32, ld, cpw, nchunks);
+                                               shifts, out_u32, out_f32, ld, tn.chunks_per_wave, nchunks,
+                                               tn.interleaved, q0);
                         });
                     } else {
                         hipLaunchKernelGGL((sobol_general<NUS.value, SH.value, SX.value, WU.value, WF.value>),
@@ -407,13 +449,13 @@ extern "C" qmc_status qmc_generate_lattice(qmc_context ctx, qmc_stream stream, c
                 with_outputs(out_u32 != nullptr, out_f32 != nullptr, [&](auto WU, auto WF) {
                     if (fast) {
                         with_bool(ctx->lattice_tune.nontemporal != 0, [&](auto NT) {
-                            uint32_t nchunks;
-                            const uint32_t cpw = ctx->lattice_tune.chunks_per_wave;
-                            const uint32_t grid = fast_grid(nn, cpw, &nchunks);
+                            uint32_t nchunks, q0;
+                            const GenTune& tn = ctx->lattice_tune;
+                            const uint32_t grid = fast_grid(nn, tn, &nchunks, &q0);
                             hipLaunchKernelGGL(
                                 (lattice_fast<BK.value, SH.value, SX.value, WU.value, WF.value, NT.value>),
                                 dim3(grid), dim3(kBlock), 0, hs, generator, s, first32, nn, shifts, out_u32, out_f32,
-                                ld, cpw, nchunks);
+                                ld, tn.chunks_per_wave, nchunks, tn.interleaved);
                         });
                     } else {
                         hipLaunchKernelGGL((lattice_general<BK.value, SH.value, SX.value, WU.value, WF.value>),

@@ -64,6 +64,7 @@ struct Args {
     float* sums;
     float* means;
     const float* grad_means;
+    const float* target;  // L2 step: per-pixel targets
     // materialised samples (plain path)
     float* out;
     uint64_t out_ld;
@@ -101,7 +102,7 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total) 
         const uint32_t y = __shfl_up(x, o, kWave);
         if (lane_id() >= static_cast<uint32_t>(o)) x += y;
     }
-    *total = __shfl(x, 63, kWave);
+    *total = __builtin_amdgcn_readfirstlane(__shfl(x, 63, kWave));
     return x - v;
 }
 
@@ -132,7 +133,7 @@ __device__ __forceinline__ uint32_t next_task(const Args& a, uint32_t wave_globa
     if (a.dynamic) {
         uint32_t t = 0;
         if (lane_id() == 0) t = atomicAdd(a.queue, 1u);
-        return __shfl(t, 0, kWave);
+        return __builtin_amdgcn_readfirstlane(t);
     }
     return wave_global + iter * a.total_waves;
 }
@@ -155,6 +156,10 @@ struct PixelLds {
     float delta[D];
     uint32_t B[D];  // current per-round index part
 };
+
+// 2^-e for e >= 0 with the hardware exponential (about 1 ulp); results below 2^-126 may flush
+// to zero, which changes a lobe's contribution by less than 1e-38.
+__device__ __forceinline__ float exp2_neg(float e) { return __builtin_amdgcn_exp2f(-e); }
 
 __device__ __forceinline__ float pixel_delta(uint32_t kd, uint32_t p) {
     const float u = dev::u32_to_unifloat(dev::pcg_hash(kd ^ p));
@@ -194,47 +199,42 @@ __device__ void stage_sampler(SamplerLds<D>& S, const Args& a) {
     }
 }
 
-// Per-dimension index part of sample i for the Sobol' sampler.  Aligned windows use the
-// per-round base (lane part from the LDS table at k); otherwise the plain matrix product
-// C_j i is formed here, looping over index bits outside and dimensions inside so that the
-// per-dimension values stay in registers.
-template <int D, uint32_t SK, bool NUS>
+// Per-dimension Sobol' index part of sample i.  With a per-round base (windows starting on a
+// multiple of 64) it is base[j] ^ T[j][k], k = i - begin < 64; otherwise the plain matrix
+// product C_j i is formed, looping over index bits outside and dimensions inside so that
+// the per-dimension values stay in registers.  Mirrored when scrambling.
+template <int D, bool NUS>
 __device__ __forceinline__ void index_part(uint32_t (&v)[D], const SamplerLds<D>& S, const Args& a, uint32_t i,
-                                           uint32_t k, const uint32_t (&base)[D], bool use_base) {
-    if constexpr (SK == QMC_SAMPLER_SOBOL) {
-        if (use_base) {
+                                           uint32_t k, const uint32_t* base) {
+    if (base) {
 #pragma unroll
-            for (int j = 0; j < D; ++j) v[j] = base[j] ^ S.T[j][k];
-        } else {
-#pragma unroll
-            for (int j = 0; j < D; ++j) v[j] = 0u;
-            for (uint32_t b = 0; b < 32; ++b) {
-                if ((i >> b) & 1u) {
-#pragma unroll
-                    for (int j = 0; j < D; ++j)
-                        if (uint32_t(j) < a.d) v[j] ^= a.table[j * 32 + b];
-                }
-            }
-            if constexpr (NUS) {
-#pragma unroll
-                for (int j = 0; j < D; ++j) v[j] = dev::brev(v[j]);
-            }
-        }
+        for (int j = 0; j < D; ++j) v[j] = base[j] ^ S.T[j][k];
     } else {
 #pragma unroll
         for (int j = 0; j < D; ++j) v[j] = 0u;
+        for (uint32_t b = 0; b < 32; ++b) {
+            if ((i >> b) & 1u) {
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    if (uint32_t(j) < a.d) v[j] ^= a.table[j * 32 + b];
+            }
+        }
+        if constexpr (NUS) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) v[j] = dev::brev(v[j]);
+        }
     }
 }
 
 // Components j < d of sample i of pixel p into x (x[j] = 0 for j >= d).
-//   k:      i - begin, the per-lane table index when use_base (k < 64);
-//   base:   per-round index part, used when use_base (else C_j i is formed directly -- any begin);
+//   base:   per-round index part in LDS (PixelLds::B or SamplerLds::B0); with it, the Sobol'
+//           index part is base[j] ^ T[j][k] for k = i - begin < 64.  NULL: C_j i directly.
 //   PX:     per-pixel values of a big pixel (NULL: derive them from the hash per lane);
 //   valid:  false for lanes past the end of a window, which must not read materialised samples.
 template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK>
 __device__ __forceinline__ void sample_point(float (&x)[D], const SamplerLds<D>& S, const PixelLds<D>* PX,
                                              const Args& a, uint32_t p, uint32_t i, uint32_t k,
-                                             const uint32_t (&base)[D], bool use_base, bool valid) {
+                                             const uint32_t* base, bool valid) {
     if constexpr (SK == QMC_SAMPLER_POINTS) {
         const uint64_t off = valid ? a.offsets[p] + i : 0;
 #pragma unroll
@@ -242,13 +242,17 @@ __device__ __forceinline__ void sample_point(float (&x)[D], const SamplerLds<D>&
             x[j] = (valid && uint32_t(j) < a.d) ? a.points[uint64_t(j) * a.points_ld + off] : 0.0f;
     } else {
         uint32_t ip[D];
-        index_part<D, SK, NUS>(ip, S, a, i, k, base, use_base);
+        if constexpr (SK == QMC_SAMPLER_SOBOL) index_part<D, NUS>(ip, S, a, i, k, base);
         const uint32_t bi = (SK == QMC_SAMPLER_LATTICE) ? dev::brev(BACK ? ~i : i) : 0u;
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             x[j] = 0.0f;
             if (uint32_t(j) < a.d) {
-                uint32_t v = (SK == QMC_SAMPLER_SOBOL) ? ip[j] : bi * S.g[j];
+                uint32_t v;
+                if constexpr (SK == QMC_SAMPLER_SOBOL)
+                    v = ip[j];
+                else
+                    v = bi * S.g[j];
                 if constexpr (NUS) {
                     uint32_t sd, sm;
                     if (PX) {
@@ -293,7 +297,7 @@ __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S,
         const uint32_t q = __builtin_ctzll(bigmask);
         bigmask &= bigmask - 1;
         const uint32_t pp = p0 + q;
-        const uint32_t nn = __shfl(n, q, kWave);
+        const uint32_t nn = __builtin_amdgcn_readfirstlane(__shfl(n, q, kWave));
         if (lane < D && lane < a.d) {
             if constexpr (NUS) {
                 const uint32_t sd = dev::pcg_hash(S.kn[lane] ^ pp);
@@ -311,11 +315,7 @@ __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S,
             const uint32_t k = r * kWave + lane;
             const uint32_t count = min(nn - r * kWave, kWave);
             float x[D];
-            uint32_t base[D];
-#pragma unroll
-            for (int j = 0; j < D; ++j)
-                base[j] = (SK == QMC_SAMPLER_SOBOL && a.aligned && uint32_t(j) < a.d) ? PX.B[j] : 0u;
-            sample_point<D, SK, NUS, SHIFT, BACK>(x, S, &PX, a, pp, a.begin + k, lane, base, a.aligned != 0,
+            sample_point<D, SK, NUS, SHIFT, BACK>(x, S, &PX, a, pp, a.begin + k, lane, a.aligned ? PX.B : nullptr,
                                                   lane < count);
             if constexpr (DELTA) {
 #pragma unroll
@@ -346,11 +346,8 @@ __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S,
         const uint32_t pp = p0 + q;
         const uint32_t k = valid ? g - offq : 0u;
         float x[D];
-        uint32_t base[D];
-#pragma unroll
-        for (int j = 0; j < D; ++j) base[j] = (SK == QMC_SAMPLER_SOBOL && a.aligned && uint32_t(j) < a.d) ? S.B0[j] : 0u;
-        sample_point<D, SK, NUS, SHIFT, BACK>(x, S, nullptr, a, pp, a.begin + k, k & (kWave - 1), base,
-                                              a.aligned != 0, valid);
+        sample_point<D, SK, NUS, SHIFT, BACK>(x, S, nullptr, a, pp, a.begin + k, k & (kWave - 1),
+                                              a.aligned ? S.B0 : nullptr, valid);
         if constexpr (DELTA) {
 #pragma unroll
             for (int j = 0; j < D; ++j) x[j] = uint32_t(j) < a.d ? x[j] + pixel_delta(S.kd[j], pp) : 0.0f;
@@ -394,7 +391,7 @@ __device__ __forceinline__ void write_pixel(const Args& a, uint32_t p, float win
 // Runs body(task) for every task this wavefront obtains.
 template <typename F>
 __device__ __forceinline__ void for_each_task(const Args& a, F&& body) {
-    const uint32_t wave_global = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const uint32_t wave_global = blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (uint32_t it = 0;; ++it) {
         const uint32_t task = next_task(a, wave_global, it);
         if (task >= a.num_tasks) break;
@@ -404,20 +401,38 @@ __device__ __forceinline__ void for_each_task(const Args& a, F&& body) {
 
 // ------------------------------------------------------------ Genz forward ----
 
-// Genz product: exp(-sum_{j<4} a_j^2 (x_j - u_j)^2) * cos(2 pi u_4 + sum_{j>=4} a_j x_j).
-__device__ __forceinline__ float genz_eval(const Args& a, uint32_t p, const float (&x)[8]) {
-    const float* pp = a.pixel_params + uint64_t(p) * 16;
-    float e = 0.0f;
+// Genz product f(x) = exp(-sum_{j<4} a_j^2 (x_j - u_j)^2) * cos(2 pi u_4 + sum_{j>=4} a_j x_j),
+// evaluated as exp2(-sum (c_j (x_j - u_j))^2) with c_j = a_j sqrt(log2 e), and the phase in
+// turns, phi = u_4 + sum_{j>=4} (a_j / 2 pi) x_j, reduced to [-1/2, 1/2] before the hardware
+// cosine (which takes its argument in turns).
+struct GenzPixel {
+    float u[4], c[4], phi0, b[4];
+    __device__ __forceinline__ void load(const Args& a, uint32_t p) {
+        const float* pp = a.pixel_params + uint64_t(p) * 16;
+        constexpr float kSqrtLog2e = 1.2011224087864498f;  // sqrt(log2(e))
+        constexpr float kInv2Pi = 0.15915494309189535f;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const float t = pp[8 + j] * (x[j] - pp[j]);
-        e = fmaf(t, t, e);
+        for (int j = 0; j < 4; ++j) {
+            u[j] = pp[j];
+            c[j] = pp[8 + j] * kSqrtLog2e;
+            b[j] = pp[12 + j] * kInv2Pi;
+        }
+        phi0 = pp[4];
     }
-    float ph = 6.28318530717958648f * pp[4];
+    __device__ __forceinline__ float eval(const float (&x)[8]) const {
+        float e = 0.0f;
 #pragma unroll
-    for (int j = 4; j < 8; ++j) ph = fmaf(pp[8 + j], x[j], ph);
-    return expf(-e) * cosf(ph);
-}
+        for (int j = 0; j < 4; ++j) {
+            const float t = c[j] * (x[j] - u[j]);
+            e = fmaf(t, t, e);
+        }
+        float ph = phi0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ph = fmaf(b[j], x[4 + j], ph);
+        ph -= rintf(ph);
+        return exp2_neg(e) * __builtin_amdgcn_cosf(ph);
+    }
+};
 
 template <uint32_t SK, bool NUS, bool SHIFT, bool BACK>
 __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
@@ -431,10 +446,22 @@ __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
     for_each_task(a, [&](uint32_t task) {
         const TileInfo ti = tile_info(a, task);
         float big_acc = 0.0f, small_acc = 0.0f;
+        GenzPixel gbig;
         walk_tile<D, SK, NUS, SHIFT, BACK, false>(
-            a, S, PX, task, ti.n, ti.inb, ti.off, ti.total, [&](uint32_t) { big_acc = 0.0f; },
+            a, S, PX, task, ti.n, ti.inb, ti.off, ti.total,
+            [&](uint32_t q) {
+                big_acc = 0.0f;
+                gbig.load(a, __builtin_amdgcn_readfirstlane(task * kTile + q));
+            },
             [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t pp, bool is_big, uint32_t slot0, uint32_t) {
-                float f = genz_eval(a, pp, x);
+                float f;
+                if (is_big) {
+                    f = gbig.eval(x);
+                } else {
+                    GenzPixel g;
+                    g.load(a, pp);
+                    f = g.eval(x);
+                }
                 if (lane >= count) f = 0.0f;
                 if (is_big) {
                     big_acc += f;
@@ -465,11 +492,14 @@ struct LobeLayout {
     static constexpr uint32_t LPG = kWave / H;
 };
 
+// Staged samples of one round.  For d > 32 a round is staged in two passes of 32 samples,
+// which halves the LDS footprint so that two blocks fit on a compute unit.
 template <int D>
 struct StageLds {
-    float y[kWave][D + 1];
-    float scale[kWave];  // adjoint weight of the sample (gI_p / N_p)
-    uint32_t q[kWave];   // tile-local pixel of the sample
+    static constexpr uint32_t kRows = D > 32 ? 32 : kWave;
+    alignas(16) float y[kRows][D + 4];  // rows padded to 16 bytes so a lane reads 4 coordinates per access
+    float scale[kRows];                 // adjoint weight of the sample (gI_p / N_p)
+    uint32_t q[kRows];                  // tile-local pixel of the sample
 };
 
 // Loads this lane's lobe parameters for group kg: st = kKappa e^-l, b = -c st (zero when the
@@ -520,9 +550,64 @@ __device__ __forceinline__ float lobe_exponent(const StageLds<D>& ST, uint32_t m
 
 // ---------------------------------------------------------- lobes forward ----
 
+// Window sums of the tile's pixels into res[q] (one wave_sum per pixel and lobe group).
+template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK>
+__device__ __forceinline__ void lobes_fwd_tile(const Args& a, const SamplerLds<D>& S, PixelLds<D>& PX,
+                                               StageLds<D>& ST, float* res, uint32_t task, const TileInfo& ti) {
+    using LL = LobeLayout<D>;
+    const uint32_t lane = lane_id();
+    const uint32_t half = lane / LL::LPG;
+    const uint32_t groups = (a.L + LL::LPG - 1) / LL::LPG;
+    res[lane] = 0.0f;
+    wave_sync();
+    for (uint32_t kg = 0; kg < groups; ++kg) {
+        float st[LL::DH], b[LL::DH], w;
+        uint32_t lobe;
+        bool own;
+        load_lobe<D>(a, kg, st, b, &w, &lobe, &own);
+        if (half != 0) w = 0.0f;  // both halves form G; one adds w G
+        float acc = 0.0f;
+        uint32_t cur = 0xFFFFFFFFu;
+        auto flush = [&]() {
+            if (cur != 0xFFFFFFFFu) {
+                const float s = wave_sum(acc);
+                if (lane == 0) res[cur] += s;
+            }
+            acc = 0.0f;
+        };
+        walk_tile<D, SK, NUS, SHIFT, BACK, true>(
+            a, S, PX, task, ti.n, ti.inb, ti.off, ti.total, [&](uint32_t) {},
+            [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t, bool, uint32_t, uint32_t) {
+                constexpr uint32_t R = StageLds<D>::kRows;
+                for (uint32_t r0 = 0; r0 < count; r0 += R) {
+                    if (lane >= r0 && lane < r0 + R) {
+#pragma unroll
+                        for (int j = 0; j < D; ++j) ST.y[lane - r0][j] = x[j];
+                        ST.q[lane - r0] = q;
+                    }
+                    wave_sync();
+                    const uint32_t mend = min(count - r0, R);
+                    for (uint32_t m = 0; m < mend; ++m) {
+                        const uint32_t qm = __builtin_amdgcn_readfirstlane(ST.q[m]);  // same for all lanes
+                        if (qm != cur) {
+                            flush();
+                            cur = qm;
+                        }
+                        float t[LL::DH];
+                        const float e = lobe_exponent<D>(ST, m, st, b, t);
+                        acc = fmaf(w, exp2_neg(e), acc);
+                    }
+                    wave_sync();
+                }
+            },
+            [&](uint32_t) {});
+        flush();
+        wave_sync();
+    }
+}
+
 template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK>
 __global__ __launch_bounds__(kBlock) void lobes_fwd(Args a) {
-    using LL = LobeLayout<D>;
     __shared__ SamplerLds<D> S;
     __shared__ PixelLds<D> PXs[kWavesPerBlock];
     __shared__ StageLds<D> STs[kWavesPerBlock];
@@ -530,98 +615,51 @@ __global__ __launch_bounds__(kBlock) void lobes_fwd(Args a) {
     stage_sampler<D, SK, NUS>(S, a);
     __syncthreads();
     const uint32_t wv = threadIdx.x >> 6;
-    PixelLds<D>& PX = PXs[wv];
-    StageLds<D>& ST = STs[wv];
-    float* res = RES[wv];
-    const uint32_t lane = lane_id();
-    const uint32_t half = lane / LL::LPG;
-    const uint32_t groups = (a.L + LL::LPG - 1) / LL::LPG;
     for_each_task(a, [&](uint32_t task) {
         const TileInfo ti = tile_info(a, task);
-        res[lane] = 0.0f;
-        wave_sync();
-        for (uint32_t kg = 0; kg < groups; ++kg) {
-            float st[LL::DH], b[LL::DH], w;
-            uint32_t lobe;
-            bool own;
-            load_lobe<D>(a, kg, st, b, &w, &lobe, &own);
-            if (half != 0) w = 0.0f;  // both halves form G; one adds w G
-            float acc = 0.0f;
-            uint32_t cur = 0xFFFFFFFFu;
-            auto flush = [&]() {
-                if (cur != 0xFFFFFFFFu) {
-                    const float s = wave_sum(acc);
-                    if (lane == 0) res[cur] += s;
-                }
-                acc = 0.0f;
-            };
-            walk_tile<D, SK, NUS, SHIFT, BACK, true>(
-                a, S, PX, task, ti.n, ti.inb, ti.off, ti.total, [&](uint32_t) {},
-                [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t, bool, uint32_t, uint32_t) {
-#pragma unroll
-                    for (int j = 0; j < D; ++j) ST.y[lane][j] = x[j];
-                    ST.q[lane] = q;
-                    wave_sync();
-                    for (uint32_t m = 0; m < count; ++m) {
-                        const uint32_t qm = ST.q[m];
-                        if (qm != cur) {
-                            flush();
-                            cur = qm;
-                        }
-                        float t[LL::DH];
-                        const float e = lobe_exponent<D>(ST, m, st, b, t);
-                        acc = fmaf(w, exp2f(-e), acc);
-                    }
-                    wave_sync();
-                },
-                [&](uint32_t) {});
-            flush();
-            wave_sync();
-        }
-        if (ti.inb) write_pixel(a, ti.p, res[lane]);
+        lobes_fwd_tile<D, SK, NUS, SHIFT, BACK>(a, S, PXs[wv], STs[wv], RES[wv], task, ti);
+        if (ti.inb) write_pixel(a, ti.p, RES[wv][lane_id()]);
         wave_sync();
     });
 }
 
 // ---------------------------------------------------------- lobes adjoint ----
 
+// Adds sum over the tile's samples of gscale(pixel) * d f / d theta into out[0 .. n_theta)
+// (c and l entries still carry the factor kKappa^2 that the reduction removes).
 template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK>
-__global__ __launch_bounds__(kBlock) void lobes_bwd(Args a) {
+__device__ __forceinline__ void lobes_bwd_tile(const Args& a, const SamplerLds<D>& S, PixelLds<D>& PX,
+                                               StageLds<D>& ST, uint32_t task, const TileInfo& ti, float gscale,
+                                               float* out) {
     using LL = LobeLayout<D>;
-    __shared__ SamplerLds<D> S;
-    __shared__ PixelLds<D> PXs[kWavesPerBlock];
-    __shared__ StageLds<D> STs[kWavesPerBlock];
-    stage_sampler<D, SK, NUS>(S, a);
-    __syncthreads();
-    const uint32_t wv = threadIdx.x >> 6;
-    PixelLds<D>& PX = PXs[wv];
-    StageLds<D>& ST = STs[wv];
     const uint32_t lane = lane_id();
     const uint32_t half = lane / LL::LPG;
     const uint32_t groups = (a.L + LL::LPG - 1) / LL::LPG;
-    for_each_task(a, [&](uint32_t task) {
-        const TileInfo ti = tile_info(a, task);
-        const uint32_t N = ti.inb ? a.counts[ti.p] : 0u;
-        const float gscale = (ti.inb && N) ? a.grad_means[ti.p] / static_cast<float>(N) : 0.0f;
-        for (uint32_t kg = 0; kg < groups; ++kg) {
-            float st[LL::DH], b[LL::DH], w;
-            uint32_t lobe;
-            bool own;
-            load_lobe<D>(a, kg, st, b, &w, &lobe, &own);
-            float acc_c[LL::DH], acc_l[LL::DH], acc_w = 0.0f;
+    for (uint32_t kg = 0; kg < groups; ++kg) {
+        float st[LL::DH], b[LL::DH], w;
+        uint32_t lobe;
+        bool own;
+        load_lobe<D>(a, kg, st, b, &w, &lobe, &own);
+        float acc_c[LL::DH], acc_l[LL::DH], acc_w = 0.0f;
 #pragma unroll
-            for (int jj = 0; jj < LL::DH; ++jj) acc_c[jj] = acc_l[jj] = 0.0f;
-            walk_tile<D, SK, NUS, SHIFT, BACK, true>(
-                a, S, PX, task, ti.n, ti.inb, ti.off, ti.total, [&](uint32_t) {},
-                [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t, bool, uint32_t, uint32_t) {
+        for (int jj = 0; jj < LL::DH; ++jj) acc_c[jj] = acc_l[jj] = 0.0f;
+        walk_tile<D, SK, NUS, SHIFT, BACK, true>(
+            a, S, PX, task, ti.n, ti.inb, ti.off, ti.total, [&](uint32_t) {},
+            [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t, bool, uint32_t, uint32_t) {
+                constexpr uint32_t R = StageLds<D>::kRows;
+                const float sc = __shfl(gscale, q, kWave);
+                for (uint32_t r0 = 0; r0 < count; r0 += R) {
+                    if (lane >= r0 && lane < r0 + R) {
 #pragma unroll
-                    for (int j = 0; j < D; ++j) ST.y[lane][j] = x[j];
-                    ST.scale[lane] = __shfl(gscale, q, kWave);
+                        for (int j = 0; j < D; ++j) ST.y[lane - r0][j] = x[j];
+                        ST.scale[lane - r0] = sc;
+                    }
                     wave_sync();
-                    for (uint32_t m = 0; m < count; ++m) {
+                    const uint32_t mend = min(count - r0, R);
+                    for (uint32_t m = 0; m < mend; ++m) {
                         float t[LL::DH];
                         const float e = lobe_exponent<D>(ST, m, st, b, t);
-                        const float aG = ST.scale[m] * exp2f(-e);
+                        const float aG = ST.scale[m] * exp2_neg(e);
                         acc_w += aG;
                         const float gw = aG * w;
 #pragma unroll
@@ -632,10 +670,148 @@ __global__ __launch_bounds__(kBlock) void lobes_bwd(Args a) {
                         }
                     }
                     wave_sync();
+                }
+            },
+            [&](uint32_t) {});
+        if (own) {
+            const uint32_t d = a.d, L = a.L;
+#pragma unroll
+            for (int jj = 0; jj < LL::DH; ++jj) {
+                const uint32_t j = half * LL::DH + jj;
+                if (j < d) {
+                    out[lobe * d + j] = acc_c[jj] * st[jj];
+                    out[L * d + lobe * d + j] = acc_l[jj];
+                }
+            }
+            if (half == 0) out[2 * L * d + lobe] = acc_w;
+        }
+    }
+}
+
+template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK>
+__global__ __launch_bounds__(kBlock) void lobes_bwd(Args a) {
+    __shared__ SamplerLds<D> S;
+    __shared__ PixelLds<D> PXs[kWavesPerBlock];
+    __shared__ StageLds<D> STs[kWavesPerBlock];
+    stage_sampler<D, SK, NUS>(S, a);
+    __syncthreads();
+    const uint32_t wv = threadIdx.x >> 6;
+    for_each_task(a, [&](uint32_t task) {
+        const TileInfo ti = tile_info(a, task);
+        const uint32_t N = ti.inb ? a.counts[ti.p] : 0u;
+        const float gscale = (ti.inb && N) ? a.grad_means[ti.p] / static_cast<float>(N) : 0.0f;
+        lobes_bwd_tile<D, SK, NUS, SHIFT, BACK>(a, S, PXs[wv], STs[wv], task, ti, gscale,
+                                                a.partials + uint64_t(task) * a.n_theta);
+    });
+}
+
+// ------------------------------------------------------ fused L2 training step ----
+//
+// L = (1/P) sum_p (I_p - T_p)^2: the estimate of each pixel, dL/dI_p = 2 (I_p - T_p) / P and
+// the adjoint over the same samples in one kernel.  Partial rows hold [dL/dtheta, loss sum].
+// The adjoint's per-pixel sums  sum_i G,  sum_i w G t_j  and  sum_i w G t_j^2  do not depend on
+// dL/dI_p, only their final scaling does; so when all lobes fit one lane group, a single pass
+// over each pixel's samples accumulates the estimate and these sums together, and at the end of
+// the pixel (a uniform event, as in the forward pass) scales them by dL/dI_p / N_p into the
+// lobe's totals.  Samples are generated once.  With more lobes than one group the estimate needs
+// every group first, so such launches (SINGLE = false) run the forward walk and then the
+// adjoint walk.
+template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK, bool SINGLE>
+__global__ __launch_bounds__(kBlock) void lobes_step(Args a) {
+    using LL = LobeLayout<D>;
+    __shared__ SamplerLds<D> S;
+    __shared__ PixelLds<D> PXs[kWavesPerBlock];
+    __shared__ StageLds<D> STs[kWavesPerBlock];
+    __shared__ float RES[kWavesPerBlock][kTile];
+    stage_sampler<D, SK, NUS>(S, a);
+    __syncthreads();
+    const uint32_t wv = threadIdx.x >> 6;
+    PixelLds<D>& PX = PXs[wv];
+    StageLds<D>& ST = STs[wv];
+    const uint32_t lane = lane_id();
+    const uint32_t half = lane / LL::LPG;
+    const float invP = 1.0f / static_cast<float>(a.num_pixels);
+    for_each_task(a, [&](uint32_t task) {
+        const TileInfo ti = tile_info(a, task);
+        float* out = a.partials + uint64_t(task) * (a.n_theta + 1);
+        if constexpr (SINGLE) {
+            float st[LL::DH], b[LL::DH], w;
+            uint32_t lobe;
+            bool own;
+            load_lobe<D>(a, 0, st, b, &w, &lobe, &own);
+            const float wf = half == 0 ? w : 0.0f;  // both halves form G; one adds it to sums
+            float acc_c[LL::DH], acc_l[LL::DH], acc_w = 0.0f, loss = 0.0f;
+            float pf = 0.0f, pw = 0.0f, pc[LL::DH], pl[LL::DH];  // the current pixel's sums
+#pragma unroll
+            for (int jj = 0; jj < LL::DH; ++jj) acc_c[jj] = acc_l[jj] = pc[jj] = pl[jj] = 0.0f;
+            uint32_t cur = 0xFFFFFFFFu;
+            auto flush = [&]() {
+                if (cur != 0xFFFFFFFFu) {
+                    const uint32_t pp = task * kTile + cur;
+                    const uint32_t N = a.counts[pp];
+                    const float I = wave_sum(pf) / static_cast<float>(N);
+                    const float diff = I - a.target[pp];
+                    if (lane == 0) {
+                        if (a.means) a.means[pp] = I;
+                        loss = fmaf(diff, diff, loss);
+                    }
+                    const float scale = 2.0f * diff * invP / static_cast<float>(N);
+                    acc_w = fmaf(scale, pw, acc_w);
+#pragma unroll
+                    for (int jj = 0; jj < LL::DH; ++jj) {
+                        acc_c[jj] = fmaf(scale, pc[jj], acc_c[jj]);
+                        acc_l[jj] = fmaf(scale, pl[jj], acc_l[jj]);
+                    }
+                }
+                pf = pw = 0.0f;
+#pragma unroll
+                for (int jj = 0; jj < LL::DH; ++jj) pc[jj] = pl[jj] = 0.0f;
+            };
+            // pixels with an empty window still get a mean (0) and their loss term
+            if (ti.inb && ti.n == 0) {
+                const float diff = 0.0f - a.target[ti.p];
+                if (a.means) a.means[ti.p] = 0.0f;
+                RES[wv][lane] = diff * diff;
+            } else {
+                RES[wv][lane] = 0.0f;
+            }
+            walk_tile<D, SK, NUS, SHIFT, BACK, true>(
+                a, S, PX, task, ti.n, ti.inb, ti.off, ti.total, [&](uint32_t) {},
+                [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t, bool, uint32_t, uint32_t) {
+                    constexpr uint32_t R = StageLds<D>::kRows;
+                    for (uint32_t r0 = 0; r0 < count; r0 += R) {
+                        if (lane >= r0 && lane < r0 + R) {
+#pragma unroll
+                            for (int j = 0; j < D; ++j) ST.y[lane - r0][j] = x[j];
+                            ST.q[lane - r0] = q;
+                        }
+                        wave_sync();
+                        const uint32_t mend = min(count - r0, R);
+#pragma nounroll
+                        for (uint32_t m = 0; m < mend; ++m) {
+                            const uint32_t qm = __builtin_amdgcn_readfirstlane(ST.q[m]);
+                            if (qm != cur) {
+                                flush();
+                                cur = qm;
+                            }
+                            float t[LL::DH];
+                            const float G = exp2_neg(lobe_exponent<D>(ST, m, st, b, t));
+                            const float wG = w * G;
+                            pf = fmaf(wf, G, pf);
+                            pw += G;
+#pragma unroll
+                            for (int jj = 0; jj < LL::DH; ++jj) {
+                                const float gt = wG * t[jj];
+                                pc[jj] += gt;
+                                pl[jj] = fmaf(gt, t[jj], pl[jj]);
+                            }
+                        }
+                        wave_sync();
+                    }
                 },
                 [&](uint32_t) {});
+            flush();
             if (own) {
-                float* out = a.partials + uint64_t(task) * a.n_theta;
                 const uint32_t d = a.d, L = a.L;
 #pragma unroll
                 for (int jj = 0; jj < LL::DH; ++jj) {
@@ -647,6 +823,25 @@ __global__ __launch_bounds__(kBlock) void lobes_bwd(Args a) {
                 }
                 if (half == 0) out[2 * L * d + lobe] = acc_w;
             }
+            const float empty_loss = wave_sum(RES[wv][lane]);
+            if (lane == 0) out[a.n_theta] = loss + empty_loss;
+            wave_sync();
+        } else {
+            // forward walk over every lobe group, per-pixel loss gradient, adjoint walk
+            lobes_fwd_tile<D, SK, NUS, SHIFT, BACK>(a, S, PX, ST, RES[wv], task, ti);
+            const uint32_t N = ti.inb ? a.counts[ti.p] : 0u;
+            float gscale = 0.0f, sq = 0.0f;
+            if (ti.inb) {
+                const float I = N ? RES[wv][lane] / static_cast<float>(N) : 0.0f;
+                const float diff = I - a.target[ti.p];
+                if (a.means) a.means[ti.p] = I;
+                sq = diff * diff;
+                gscale = N ? 2.0f * diff * invP / static_cast<float>(N) : 0.0f;
+            }
+            const float loss = wave_sum(sq);
+            wave_sync();
+            lobes_bwd_tile<D, SK, NUS, SHIFT, BACK>(a, S, PX, ST, task, ti, gscale, out);
+            if (lane == 0) out[a.n_theta] = loss;
         }
     });
 }
@@ -674,15 +869,21 @@ __global__ __launch_bounds__(256) void reduce_partials_chunks(const float* __res
 }
 
 // Second level: grad[e] += scale_e * sum over chunks in chunk order; the centre and log-width
-// entries carry the factor 1/kKappa^2 of the exp2 form.
-__global__ void reduce_chunks(const double* __restrict__ chunk_sums, uint32_t num_chunks, uint32_t n_theta,
-                              uint32_t LD, float* __restrict__ grad) {
+// entries carry the factor 1/kKappa^2 of the exp2 form.  Rows of n_row = n_theta (+1 with a
+// loss sum in the last entry, which is added to *loss as a mean over the pixels).
+__global__ void reduce_chunks(const double* __restrict__ chunk_sums, uint32_t num_chunks, uint32_t n_row,
+                              uint32_t n_theta, uint32_t LD, float* __restrict__ grad, float* __restrict__ loss,
+                              uint32_t num_pixels) {
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n_theta) return;
+    if (e >= n_row) return;
     double acc = 0.0;
-    for (uint32_t c = 0; c < num_chunks; ++c) acc += chunk_sums[uint64_t(c) * n_theta + e];
-    const double scale = e < 2 * LD ? 1.0 / (static_cast<double>(kKappa) * kKappa) : 1.0;
-    grad[e] += static_cast<float>(acc * scale);
+    for (uint32_t c = 0; c < num_chunks; ++c) acc += chunk_sums[uint64_t(c) * n_row + e];
+    if (e < n_theta) {
+        const double scale = e < 2 * LD ? 1.0 / (static_cast<double>(kKappa) * kKappa) : 1.0;
+        grad[e] += static_cast<float>(acc * scale);
+    } else if (loss) {
+        *loss += static_cast<float>(acc / num_pixels);
+    }
 }
 
 __global__ void reset_queue(uint32_t* q) { *q = 0u; }
@@ -763,17 +964,19 @@ __global__ __launch_bounds__(256) void scan_add(uint64_t* __restrict__ offsets, 
 
 struct Plan {
     size_t queue_off = 0, partials_off = 256, chunks_off = 256, total = 256;
-    uint32_t num_tasks = 0, num_chunks = 0, n_theta = 0;
+    uint32_t num_tasks = 0, num_chunks = 0, n_theta = 0, n_row = 0;
 };
 
-Plan make_plan(const qmc_integrand* ig, uint32_t P, bool backward) {
+// mode: 0 forward, 1 adjoint, 2 fused L2 step (partial rows carry one extra loss entry).
+Plan make_plan(const qmc_integrand* ig, uint32_t P, int mode) {
     Plan pl;
     pl.num_tasks = (P + kTile - 1) / kTile;
     pl.num_chunks = (pl.num_tasks + kChunkTasks - 1) / kChunkTasks;
     if (ig && ig->kind == QMC_F_LOBES) pl.n_theta = ig->num_lobes * (2 * ig->d + 1);
-    if (backward) {
-        pl.chunks_off = (pl.partials_off + size_t(pl.num_tasks) * pl.n_theta * 4 + 255) & ~size_t(255);
-        pl.total = pl.chunks_off + size_t(pl.num_chunks) * pl.n_theta * 8;
+    pl.n_row = pl.n_theta + (mode == 2 ? 1u : 0u);
+    if (mode != 0) {
+        pl.chunks_off = (pl.partials_off + size_t(pl.num_tasks) * pl.n_row * 4 + 255) & ~size_t(255);
+        pl.total = pl.chunks_off + size_t(pl.num_chunks) * pl.n_row * 8;
     }
     return pl;
 }
@@ -869,6 +1072,15 @@ struct LobesBwdFam {
     }
 };
 
+template <int D, bool SINGLE>
+struct LobesStepFam {
+    static constexpr bool kPoints = true;
+    template <uint32_t SK, bool NUS, bool SH, bool BK>
+    static void go(uint32_t grid, hipStream_t hs, const Args& a) {
+        hipLaunchKernelGGL((lobes_step<D, SK, NUS, SH, BK, SINGLE>), dim3(grid), dim3(kBlock), 0, hs, a);
+    }
+};
+
 struct SamplesFam {
     static constexpr bool kPoints = false;
     template <uint32_t SK, bool NUS, bool SH, bool BK>
@@ -908,17 +1120,20 @@ uint32_t persistent_grid(const qmc_context ctx, const IntegrateTune& tn, uint32_
     return grid;
 }
 
+// mode 0: forward; 1: adjoint; 2: fused L2 step (grad_means is the target, sums the loss).
 qmc_status integrate_common(const char* who, qmc_context ctx, qmc_stream stream, const qmc_sampler* sp,
                             const qmc_integrand* ig, uint32_t W, uint32_t H, const uint32_t* counts, uint32_t begin,
                             uint32_t end, float* sums, float* means, const float* grad_means, float* grad_params,
-                            void* ws, size_t ws_bytes, bool backward) {
+                            void* ws, size_t ws_bytes, int mode) {
+    const bool backward = mode != 0;
     qmc_status st = validate(who, ctx, sp, ig, W, H, counts, begin, end, backward);
     if (st != QMC_OK) return st;
-    if (!backward && !sums && !means) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: sums and means are both NULL", who);
+    if (mode == 0 && !sums && !means) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: sums and means are both NULL", who);
     if (backward && (!grad_means || !grad_params))
-        return fail(QMC_ERR_INVALID_ARGUMENT, "%s: grad_means and grad_params are required", who);
+        return fail(QMC_ERR_INVALID_ARGUMENT, "%s: %s and grad_params are required", who,
+                    mode == 2 ? "target" : "grad_means");
     const uint32_t P = W * H;
-    const Plan pl = make_plan(ig, P, backward);
+    const Plan pl = make_plan(ig, P, mode);
     if (!ws || ws_bytes < pl.total)
         return fail(QMC_ERR_WORKSPACE, "%s: workspace of %zu bytes needed, %zu given", who, pl.total, ws_bytes);
     DeviceGuard guard(ctx->device);
@@ -930,9 +1145,10 @@ qmc_status integrate_common(const char* who, qmc_context ctx, qmc_stream stream,
     a.pixel_seed = ig->pixel_seed;
     a.params = ig->params;
     a.pixel_params = ig->pixel_params;
-    a.sums = sums;
+    a.sums = mode == 2 ? nullptr : sums;
     a.means = means;
-    a.grad_means = grad_means;
+    a.grad_means = mode == 2 ? nullptr : grad_means;
+    a.target = mode == 2 ? grad_means : nullptr;
     a.queue = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.queue_off);
     a.partials = reinterpret_cast<float*>(static_cast<char*>(ws) + pl.partials_off);
     a.n_theta = pl.n_theta;
@@ -949,15 +1165,27 @@ qmc_status integrate_common(const char* who, qmc_context ctx, qmc_stream stream,
         else
             dispatch_sampler<LobesFwdFam<64>>(sp->kind, nus, shift, back, grid, hs, a);
     } else {
-        if (ig->d <= 8)
-            dispatch_sampler<LobesBwdFam<8>>(sp->kind, nus, shift, back, grid, hs, a);
-        else
-            dispatch_sampler<LobesBwdFam<64>>(sp->kind, nus, shift, back, grid, hs, a);
+        if (mode == 1) {
+            if (ig->d <= 8)
+                dispatch_sampler<LobesBwdFam<8>>(sp->kind, nus, shift, back, grid, hs, a);
+            else
+                dispatch_sampler<LobesBwdFam<64>>(sp->kind, nus, shift, back, grid, hs, a);
+        } else if (ig->d <= 8) {
+            if (ig->num_lobes <= LobeLayout<8>::LPG)
+                dispatch_sampler<LobesStepFam<8, true>>(sp->kind, nus, shift, back, grid, hs, a);
+            else
+                dispatch_sampler<LobesStepFam<8, false>>(sp->kind, nus, shift, back, grid, hs, a);
+        } else {
+            if (ig->num_lobes <= LobeLayout<64>::LPG)
+                dispatch_sampler<LobesStepFam<64, true>>(sp->kind, nus, shift, back, grid, hs, a);
+            else
+                dispatch_sampler<LobesStepFam<64, false>>(sp->kind, nus, shift, back, grid, hs, a);
+        }
         double* chunk_sums = reinterpret_cast<double*>(static_cast<char*>(ws) + pl.chunks_off);
-        hipLaunchKernelGGL(reduce_partials_chunks, dim3((pl.n_theta + 63) / 64, pl.num_chunks), dim3(256), 0, hs,
-                           a.partials, pl.num_tasks, pl.n_theta, chunk_sums);
-        hipLaunchKernelGGL(reduce_chunks, dim3((pl.n_theta + 255) / 256), dim3(256), 0, hs, chunk_sums,
-                           pl.num_chunks, pl.n_theta, ig->num_lobes * ig->d, grad_params);
+        hipLaunchKernelGGL(reduce_partials_chunks, dim3((pl.n_row + 63) / 64, pl.num_chunks), dim3(256), 0, hs,
+                           a.partials, pl.num_tasks, pl.n_row, chunk_sums);
+        hipLaunchKernelGGL(reduce_chunks, dim3((pl.n_row + 255) / 256), dim3(256), 0, hs, chunk_sums, pl.num_chunks,
+                           pl.n_row, pl.n_theta, ig->num_lobes * ig->d, grad_params, mode == 2 ? sums : nullptr, P);
     }
     return check_launch(who);
 }
@@ -971,7 +1199,8 @@ extern "C" qmc_status qmc_workspace_size(qmc_context ctx, const qmc_sampler* sam
                                          uint32_t width, uint32_t height, int backward, size_t* bytes) {
     if (!ctx || !sampler || !integrand || !bytes)
         return fail(QMC_ERR_INVALID_ARGUMENT, "qmc_workspace_size: NULL argument");
-    *bytes = make_plan(integrand, width * height, backward != 0).total;
+    if (backward < 0 || backward > 2) return fail(QMC_ERR_INVALID_ARGUMENT, "qmc_workspace_size: mode must be 0, 1 or 2");
+    *bytes = make_plan(integrand, width * height, backward).total;
     return QMC_OK;
 }
 
@@ -980,8 +1209,7 @@ extern "C" qmc_status qmc_integrate_pixels(qmc_context ctx, qmc_stream stream, c
                                            const uint32_t* counts, uint32_t sample_begin, uint32_t sample_end,
                                            float* sums, float* means, void* workspace, size_t workspace_bytes) {
     return integrate_common("qmc_integrate_pixels", ctx, stream, sampler, integrand, width, height, counts,
-                            sample_begin, sample_end, sums, means, nullptr, nullptr, workspace, workspace_bytes,
-                            false);
+                            sample_begin, sample_end, sums, means, nullptr, nullptr, workspace, workspace_bytes, 0);
 }
 
 extern "C" qmc_status qmc_integrate_pixels_backward(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
@@ -991,7 +1219,18 @@ extern "C" qmc_status qmc_integrate_pixels_backward(qmc_context ctx, qmc_stream 
                                                     void* workspace, size_t workspace_bytes) {
     return integrate_common("qmc_integrate_pixels_backward", ctx, stream, sampler, integrand, width, height, counts,
                             sample_begin, sample_end, nullptr, nullptr, grad_means, grad_params, workspace,
-                            workspace_bytes, true);
+                            workspace_bytes, 1);
+}
+
+extern "C" qmc_status qmc_integrate_pixels_l2_step(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
+                                                   const qmc_integrand* integrand, uint32_t width, uint32_t height,
+                                                   const uint32_t* counts, const float* target, float* means,
+                                                   float* loss, float* grad_params, void* workspace,
+                                                   size_t workspace_bytes) {
+    const char* who = "qmc_integrate_pixels_l2_step";
+    if (!loss) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: loss is NULL", who);
+    return integrate_common(who, ctx, stream, sampler, integrand, width, height, counts, 0u, 0xFFFFFFFFu, loss, means,
+                            target, grad_params, workspace, workspace_bytes, 2);
 }
 
 extern "C" qmc_status qmc_sample_offsets(qmc_context ctx, qmc_stream stream, const uint32_t* counts,

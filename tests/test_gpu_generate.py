@@ -190,3 +190,37 @@ def test_argument_errors(qmc):
     with pytest.raises(qmc.QMCError) as e:
         qmc.qmc_generate_sobol(big, 0, 10)
     assert e.value.status == 2
+
+
+@pytest.mark.parametrize("order", ["contiguous", "interleaved"])
+def test_both_chunk_orders_bit_exact(qmc, order, tmp_path):
+    """The two wavefront-to-chunk orders (set through a tuning file) give identical points."""
+    import json
+
+    import torch
+
+    f = tmp_path / "tune.json"
+    cfg = {"interleaved": 1 if order == "interleaved" else 0, "chunks_per_wave": 3, "waves": 64, "nontemporal": 0}
+    f.write_text(json.dumps({"sobol": cfg, "lattice": cfg, "integrate": []}))
+    saved = tmp_path / "saved.json"
+    qmc.qmc_tune_save(str(saved))
+    try:
+        qmc.qmc_tune_load(str(f))
+        for s, first, n, flags in ((16, 0, 64 * 256 * 5 + 33, 0), (9, 4 * 999, 100001, XOR)):
+            gu, gf, eu, ef = _run_sobol(qmc, s, first, n, True, True, flags)
+            assert np.array_equal(gu, eu) and np.array_equal(gf, ef), (order, s, first, n)
+            lu, lf, leu, lef = _run_lattice(qmc, s, 30, first, n, True, flags | BACK)
+            assert np.array_equal(lu, leu) and np.array_equal(lf, lef), (order, s, first, n)
+    finally:
+        qmc.qmc_tune_load(str(saved))
+    torch.cuda.synchronize()
+
+
+def test_autotune_generate_reports_candidates(qmc):
+    mats = qmc.from_u32(_mats(8))
+    rep = qmc.qmc_autotune_generate(qmc.QMC_SAMPLER_SOBOL, mats, 1 << 18, qmc.from_u32(nus_seeds(8, 1)),
+                                    qmc.from_u32(cp_shifts(8, 2)))
+    lines = [l for l in rep.splitlines() if l.strip()]
+    assert len(lines) == 20 and all('"ms"' in l for l in lines)
+    gu, gf, eu, ef = _run_sobol(qmc, 8, 0, 70000, True, True)
+    assert np.array_equal(gu, eu) and np.array_equal(gf, ef)

@@ -336,3 +336,29 @@ def test_integration_argument_errors(qmc):
     with pytest.raises(qmc.QMCError) as e:
         qmc.qmc_integrate_pixels(ds, ig, W, H, dc, workspace=ws)
     assert e.value.status == 5
+
+
+@pytest.mark.parametrize("d,L,W,H,cname", [(8, 64, 40, 8, "64"), (8, 64, 23, 5, "edge"), (8, 100, 16, 4, "64"),
+                                           (64, 32, 6, 4, "64"), (5, 7, 13, 4, "edge")])
+def test_fused_l2_step_matches_oracle(qmc, d, L, W, H, cname):
+    """The fused forward + L2 gradient + adjoint kernel: loss, means and dL/dtheta against
+    the FP64 oracle (the 64-spp tiles take the register-reuse path, the others two passes)."""
+    import torch
+
+    P = W * H
+    counts = counts_uniform(W, H, 64) if cname == "64" else _counts_edge(P)
+    theta, dtheta = _lobes_setup(qmc, L, d)
+    ds, os_ = _sampler_pair(qmc, "sobol", max(d, 8), 21, NUS | SHIFT)
+    ig = qmc.PixelIntegrand.lobes(dtheta, L, d, 9)
+    oig = {"kind": "lobes", "d": d, "num_lobes": L, "params": theta, "pixel_seed": 9}
+    target = estimator.integrate_pixels(os_, dict(oig, params=perturb(theta, 7)), counts, range(P))["mean"]
+    loss64, g64, means64 = estimator.loss_and_gradient(os_, oig, counts, range(P), target)
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    means, loss, grad = qmc.qmc_integrate_pixels_l2_step(ds, ig, W, H, dc, torch.from_numpy(target.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    ref = estimator.integrate_pixels(os_, oig, counts, range(P))
+    assert _est_tol(means.cpu().numpy(), ref).all()
+    g = grad.cpu().numpy().astype(np.float64)
+    ok = np.abs(g - g64) <= 1e-4 * np.maximum(np.abs(g64), 1e-3 * np.max(np.abs(g64)))
+    assert ok.all(), (np.nonzero(~ok)[0][:10], g[~ok][:5], g64[~ok][:5])
+    assert abs(float(loss.cpu()[0]) - loss64) <= 1e-4 * loss64
