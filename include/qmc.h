@@ -282,8 +282,8 @@ qmc_status qmc_integrate_progressive(qmc_context ctx, qmc_stream stream, const q
 
 /* ------------------------------------------------------------- autotuning ---- */
 
-/* Times each launch shape of the materialising kernels (chunks per wavefront 1..32, with and
- * without non-temporal stores) on `stream` with hipEvents and keeps the fastest in the context
+/* Times each launch shape of the materialising kernels (1, 2, 4 or 8 chunks of 256 indices per
+ * wavefront, with and without non-temporal stores) on `stream` with hipEvents and keeps the fastest in the context
  * for that sequence kind.  The candidates write the n points of `table` into the caller's
  * scratch buffers ([s][n] each; either may be NULL but not both).  Synchronises `stream`
  * (not capturable).  report (may be NULL) receives one JSON line per candidate.

@@ -33,10 +33,8 @@ inline qmc_status ok() { return QMC_OK; }
 
 // Launch parameters chosen for one kernel family (defaults, or picked by the autotuner).
 struct GenTune {
-    uint32_t interleaved = 1;      // 1: wavefront w takes chunks w, w+W, ...; 0: contiguous runs
-    uint32_t chunks_per_wave = 8;  // contiguous runs: 256-index chunks per wavefront and dimension
-    uint32_t waves = 8192;         // interleaved: wavefronts in the grid (rounded down to a power of two)
-    uint32_t nontemporal = 1;      // streaming (non-temporal) stores for materialised points
+    uint32_t chunks_per_wave = 1;  // consecutive 256-index chunks of one dimension per wavefront
+    uint32_t nontemporal = 0;      // streaming (non-temporal) stores for materialised points
 };
 
 struct IntegrateTune {

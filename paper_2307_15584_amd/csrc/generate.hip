@@ -2,16 +2,22 @@
 // sequences (Sec. 2.4, Eq. R1LS), randomised in integers and converted by
 // map_u32_to_unifloat (Sec. 2.1, Alg. 1).
 //
-// Output is dimension-major, out[j*ld + (i - first)].  The fast kernels give each lane four
-// consecutive indices, so a wavefront writes 256 consecutive u32 (1 KiB) per dimension with
-// 16-byte stores, and each wavefront owns a run of such 256-index chunks.  For one
-// dimension the run is generated with a single register of state:
-//   * the first point of the run is the plain matrix product (one select-XOR per index bit);
-//   * the four indices 4q..4q+3 of a lane differ only in bits 0 and 1, so their points are
-//     x, x^C[0], x^C[1], x^C[0]^C[1];
-//   * moving a lane from index i to i+256 flips index bits 8..8+t, t = ctz((i>>8)+1), so
-//     x(i+256) = x(i) ^ Q[t] with Q[t] = C[8]^...^C[8+t], a table built once per block.
-// With scrambling the columns are staged bit-reversed, which yields the mirrored value the
+// Output is dimension-major, out[j*ld + (i - first)].  The fast kernels launch one wavefront
+// per (dimension, run of `cpw` chunks of 256 indices), in dimension-major order, so that the
+// wavefronts in flight at any moment write one narrow, advancing window of each output array:
+// the access order of a plain fill, which is what the HBM write path sustains best.  Each lane
+// takes four consecutive indices and writes them with one 16-byte store per output array.
+//
+// For a digital sequence the point of index i is the XOR of the columns selected by the bits
+// of i.  With i = 256 h + t (t the lane's offset within the chunk, bits 0..7 after the carry
+// is split off):
+//   * the part from bits 8..31 (the chunk, wave-uniform) is formed by lanes 8..31 each
+//     contributing one column, then an XOR reduction across the half-wavefront; the other
+//     half-wavefront forms the part for h + 1, needed by lanes whose offset carries into bit 8
+//     when `first` is not a multiple of 256;
+//   * the part from bits 2..7 is fixed per lane and formed once;
+//   * the four indices of a lane differ in bits 0 and 1: x, x^C[0], x^C[1], x^C[0]^C[1].
+// With scrambling the columns are bit-reversed first, which yields the mirrored value the
 // nested scramble starts from at no cost.  Every kernel here switches its wavefronts to
 // round-toward-zero FP32 rounding on entry, so the float conversion is the hardware
 // u32 -> f32 conversion (which then truncates) followed by an exact scaling by 2^-32.
@@ -24,10 +30,9 @@ namespace {
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr uint32_t kBlock = 256;
-constexpr uint32_t kWavesPerBlock = kBlock / 64;
+constexpr uint32_t kBlock = 256;  // block size of the general (any alignment) kernels
+constexpr uint32_t kWave = 64;    // the fast kernels run one wavefront per block
 constexpr uint32_t kChunk = 256;  // indices per wavefront step
-constexpr uint32_t kQ = 24;       // stride-table entries per dimension (index bits 8..31)
 
 template <bool NT, typename V>
 __device__ __forceinline__ void store_vec(V* p, V v) {
@@ -72,18 +77,14 @@ __device__ __forceinline__ void emit4(uint32_t* ou, float* of, uint64_t off, uin
 
 struct SobolLds {
     uint32_t cols[QMC_MAX_DIMS][32];
-    uint32_t q[QMC_MAX_DIMS][kQ];
     uint32_t seed[QMC_MAX_DIMS];
     uint32_t sm[QMC_MAX_DIMS];
     uint32_t shift[QMC_MAX_DIMS];
 };
 
-// Q[j][t] = XOR of columns q0..q0+t of dimension j: moving an index by 2^q0 flips its bits
-// q0..q0+t with t = ctz((i >> q0) + 1), so the point moves by Q[j][t].
 template <bool NUS, bool SHIFT>
 __device__ __forceinline__ void stage_sobol(SobolLds& L, const uint32_t* __restrict__ mats, uint32_t s,
-                                            const uint32_t* __restrict__ seeds, const uint32_t* __restrict__ shifts,
-                                            bool build_q, uint32_t q0 = 8) {
+                                            const uint32_t* __restrict__ seeds, const uint32_t* __restrict__ shifts) {
     const uint32_t tid = threadIdx.x;
     for (uint32_t t = tid; t < s * 32; t += blockDim.x) {
         const uint32_t c = mats[t];
@@ -97,15 +98,6 @@ __device__ __forceinline__ void stage_sobol(SobolLds& L, const uint32_t* __restr
         if constexpr (SHIFT) L.shift[t] = shifts[t];
     }
     __syncthreads();
-    if (build_q) {
-        for (uint32_t t = tid; t < s * kQ; t += blockDim.x) {
-            const uint32_t j = t / kQ, k = t % kQ;
-            uint32_t acc = 0;
-            for (uint32_t b = 0; b <= k && q0 + b < 32; ++b) acc ^= L.cols[j][q0 + b];
-            L.q[j][k] = acc;
-        }
-        __syncthreads();
-    }
 }
 
 __device__ __forceinline__ uint32_t matrix_product(const uint32_t* cols, uint32_t i) {
@@ -115,57 +107,64 @@ __device__ __forceinline__ uint32_t matrix_product(const uint32_t* cols, uint32_
     return x;
 }
 
-// Chunk order: wavefront w handles chunks c0 + k * step for k < steps, where
-//   contiguous runs: c0 = w * steps, step = 1;
-//   interleaved:     c0 = w, step = W (all wavefronts, a power of two), so at every step the
-//                    whole grid writes one contiguous window of W chunks per output array.
-// step * 256 = 2^q0 indices, and the Q table is built from column q0.
+// XOR of v over the 32 lanes of each half-wavefront, returned to lanes 31 and 63 (other lanes
+// receive partial sums).  DPP: XOR within quads, across the quads of each row of 16 lanes
+// (rotations by 4 and 8), then row 0 (2) into row 1 (3) with a broadcast of lane 15.
+__device__ __forceinline__ uint32_t half_wave_xor(uint32_t v) {
+    const int x = static_cast<int>(v);
+    int r = x ^ __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    r ^= __builtin_amdgcn_update_dpp(0, r, 0x4E, 0xF, 0xF, false);          // quad_perm [2,3,0,1]
+    r ^= __builtin_amdgcn_update_dpp(0, r, 0x124, 0xF, 0xF, false);         // row_ror 4
+    r ^= __builtin_amdgcn_update_dpp(0, r, 0x128, 0xF, 0xF, false);         // row_ror 8
+    r ^= __builtin_amdgcn_update_dpp(0, r, 0x142, 0xA, 0xF, false);         // row_bcast 15 into rows 1, 3
+    return static_cast<uint32_t>(r);
+}
+
+// Block (x, j): dimension j, chunks [x * cpw, min((x + 1) * cpw, nchunks)).  Needs first % 4 == 0,
+// ld % 4 == 0 and 16-byte aligned outputs; n <= 2^31 and first + n <= 2^32.
 template <bool NUS, bool SHIFT, bool SXOR, bool WU, bool WF, bool NT>
-__global__ __launch_bounds__(kBlock) void sobol_fast(const uint32_t* __restrict__ mats, uint32_t s, uint32_t first,
-                                                     uint32_t n, const uint32_t* __restrict__ seeds,
-                                                     const uint32_t* __restrict__ shifts, uint32_t* __restrict__ ou,
-                                                     float* __restrict__ of, uint64_t ld, uint32_t steps,
-                                                     uint32_t nchunks, uint32_t interleaved, uint32_t q0) {
+__global__ __launch_bounds__(kWave) void sobol_fast(const uint32_t* __restrict__ mats, uint32_t first, uint32_t n,
+                                                    const uint32_t* __restrict__ seeds,
+                                                    const uint32_t* __restrict__ shifts, uint32_t* __restrict__ ou,
+                                                    float* __restrict__ of, uint64_t ld, uint32_t cpw,
+                                                    uint32_t nchunks) {
     dev::set_fp32_round_toward_zero();
-    __shared__ SobolLds L;
-    stage_sobol<NUS, SHIFT>(L, mats, s, seeds, shifts, true, q0);
-    const uint32_t wave = blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t step = interleaved ? gridDim.x * kWavesPerBlock : 1u;
-    const uint32_t c0 = interleaved ? wave : wave * steps;
-    if (c0 >= nchunks) return;
-    const uint32_t kmax = interleaved ? (nchunks - c0 + step - 1) / step : min(steps, nchunks - c0);
-    const uint32_t full = n / kChunk;  // chunks with all 256 indices in range
-    const uint32_t stride = step * kChunk;
-    for (uint32_t j = 0; j < s; ++j) {
-        uint32_t c = c0;
-        uint32_t o = c0 * kChunk + 4u * lane;
-        uint32_t i = first + o;
-        uint32_t x = matrix_product(L.cols[j], i);
-        const uint32_t col0 = L.cols[j][0], col1 = L.cols[j][1];
-        const uint32_t seed = NUS ? L.seed[j] : 0u, sm = NUS ? L.sm[j] : 0u;
-        const uint32_t sh = SHIFT ? L.shift[j] : 0u;
-        const uint64_t base = uint64_t(j) * ld;
-        for (uint32_t k = 0; k < kmax; ++k) {
-            uint32_t v0 = x, v1 = x ^ col0, v2 = x ^ col1, v3 = x ^ col0 ^ col1;
-            if constexpr (NUS) {
-                v0 = dev::nus_from_mirrored(v0, seed, sm);
-                v1 = dev::nus_from_mirrored(v1, seed, sm);
-                v2 = dev::nus_from_mirrored(v2, seed, sm);
-                v3 = dev::nus_from_mirrored(v3, seed, sm);
-            }
-            if (c < full)
-                emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, 4u, v0, v1, v2, v3, sh);
-            else if (o < n)
-                emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, min(n - o, 4u), v0, v1, v2, v3, sh);
-            if (k + 1 < kmax) {
-                const uint32_t t = min(static_cast<uint32_t>(__builtin_ctz((i >> q0) + 1u)), kQ - 1);
-                x ^= L.q[j][t];
-                i += stride;
-                o += stride;
-                c += step;
-            }
+    const uint32_t j = blockIdx.y;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t cb = blockIdx.x * cpw;
+    const uint32_t ce = min(cb + cpw, nchunks);
+    uint32_t col = mats[j * 32 + (lane & 31)];  // lane k (and k + 32) holds column k
+    if constexpr (NUS) col = dev::brev(col);
+    const uint32_t seed = NUS ? seeds[j] : 0u;
+    const uint32_t sm = dev::seed_multiplier(seed);
+    const uint32_t sh = SHIFT ? shifts[j] : 0u;
+    // i = first + 256 c + 4 lane + r = 256 (first/256 + c) + t + r with t = first%256 + 4 lane < 512.
+    const uint32_t t = (first & 255u) + 4u * lane;
+    const uint32_t carry = 0u - (t >> 8);  // all ones where the offset carries into bit 8
+    uint32_t xlo = 0;
+#pragma unroll
+    for (int k = 2; k < 8; ++k) xlo ^= (0u - ((t >> k) & 1u)) & __builtin_amdgcn_readlane(col, k);
+    const uint32_t col0 = __builtin_amdgcn_readlane(col, 0), col1 = __builtin_amdgcn_readlane(col, 1);
+    const uint32_t k = lane & 31u;
+    const uint64_t base = uint64_t(j) * ld;
+    for (uint32_t c = cb; c < ce; ++c) {
+        // Lanes 8..31 select column k for bit k of 256 h, lanes 40..63 the same for 256 (h + 1).
+        const uint32_t h = (first >> 8) + c + (lane >> 5);
+        const uint32_t part = half_wave_xor((k >= 8u && ((h >> (k - 8u)) & 1u)) ? col : 0u);
+        const uint32_t p0 = __builtin_amdgcn_readlane(part, 31), p1 = __builtin_amdgcn_readlane(part, 63);
+        const uint32_t x = (p0 ^ ((p0 ^ p1) & carry)) ^ xlo;
+        uint32_t v0 = x, v1 = x ^ col0, v2 = x ^ col1, v3 = x ^ col0 ^ col1;
+        if constexpr (NUS) {
+            v0 = dev::nus_from_mirrored(v0, seed, sm);
+            v1 = dev::nus_from_mirrored(v1, seed, sm);
+            v2 = dev::nus_from_mirrored(v2, seed, sm);
+            v3 = dev::nus_from_mirrored(v3, seed, sm);
         }
+        const uint32_t o = c * kChunk + 4u * lane;
+        if (o + 4u <= n)
+            emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, 4u, v0, v1, v2, v3, sh);
+        else if (o < n)
+            emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, n - o, v0, v1, v2, v3, sh);
     }
 }
 
@@ -177,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void sobol_general(const uint32_t* __restri
                                                         float* __restrict__ of, uint64_t ld) {
     dev::set_fp32_round_toward_zero();
     __shared__ SobolLds L;
-    stage_sobol<NUS, SHIFT>(L, mats, s, seeds, shifts, false);
+    stage_sobol<NUS, SHIFT>(L, mats, s, seeds, shifts);
     for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < n; o += gridDim.x * kBlock) {
         const uint32_t i = first + o;
         for (uint32_t j = 0; j < s; ++j) {
@@ -207,49 +206,40 @@ __device__ __forceinline__ void stage_lattice(LatticeLds& L, const uint32_t* __r
 
 // brev(i + r) = brev(i) | brev(r) for i % 4 == 0 and r < 4, so the four points of a lane are
 // x0 + brev(r) g (forward) or x0 - brev(r) g with x0 = ~brev(i) g (backward), brev(1) = 2^31,
-// brev(2) = 2^30.
+// brev(2) = 2^30.  Block (x, j): dimension j, chunks [x * cpw, min((x + 1) * cpw, nchunks)).
 template <bool BACK, bool SHIFT, bool SXOR, bool WU, bool WF, bool NT>
-__global__ __launch_bounds__(kBlock) void lattice_fast(const uint32_t* __restrict__ gen, uint32_t s, uint32_t first,
-                                                       uint32_t n, const uint32_t* __restrict__ shifts,
-                                                       uint32_t* __restrict__ ou, float* __restrict__ of, uint64_t ld,
-                                                       uint32_t cpw, uint32_t nchunks, uint32_t interleaved) {
+__global__ __launch_bounds__(kWave) void lattice_fast(const uint32_t* __restrict__ gen, uint32_t first, uint32_t n,
+                                                      const uint32_t* __restrict__ shifts, uint32_t* __restrict__ ou,
+                                                      float* __restrict__ of, uint64_t ld, uint32_t cpw,
+                                                      uint32_t nchunks) {
     dev::set_fp32_round_toward_zero();
-    __shared__ LatticeLds L;
-    stage_lattice<SHIFT>(L, gen, s, shifts);
-    const uint32_t wave = blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t step = interleaved ? gridDim.x * kWavesPerBlock : 1u;
-    const uint32_t c0 = interleaved ? wave : wave * cpw;
-    if (c0 >= nchunks) return;
-    const uint32_t kmax = interleaved ? (nchunks - c0 + step - 1) / step : min(cpw, nchunks - c0);
-    const uint32_t full = n / kChunk;
-    for (uint32_t j = 0; j < s; ++j) {
-        const uint32_t g = L.g[j];
-        const uint32_t h1 = g << 31, h2 = g << 30, h3 = h1 + h2;
-        const uint32_t sh = SHIFT ? L.shift[j] : 0u;
-        const uint64_t base = uint64_t(j) * ld;
-        for (uint32_t k = 0; k < kmax; ++k) {
-            const uint32_t c = c0 + k * step;
-            const uint32_t o = c * kChunk + 4u * lane;
-            if (c >= full && o >= n) break;
-            const uint32_t b = dev::brev(first + o);
-            uint32_t v0, v1, v2, v3;
-            if constexpr (BACK) {
-                v0 = (~b) * g;
-                v1 = v0 - h1;
-                v2 = v0 - h2;
-                v3 = v0 - h3;
-            } else {
-                v0 = b * g;
-                v1 = v0 + h1;
-                v2 = v0 + h2;
-                v3 = v0 + h3;
-            }
-            if (c < full)
-                emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, 4u, v0, v1, v2, v3, sh);
-            else
-                emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, min(n - o, 4u), v0, v1, v2, v3, sh);
+    const uint32_t j = blockIdx.y;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t cb = blockIdx.x * cpw;
+    const uint32_t ce = min(cb + cpw, nchunks);
+    const uint32_t g = gen[j];
+    const uint32_t h1 = g << 31, h2 = g << 30, h3 = h1 + h2;
+    const uint32_t sh = SHIFT ? shifts[j] : 0u;
+    const uint64_t base = uint64_t(j) * ld;
+    for (uint32_t c = cb; c < ce; ++c) {
+        const uint32_t o = c * kChunk + 4u * lane;
+        const uint32_t b = dev::brev(first + o);
+        uint32_t v0, v1, v2, v3;
+        if constexpr (BACK) {
+            v0 = (~b) * g;
+            v1 = v0 - h1;
+            v2 = v0 - h2;
+            v3 = v0 - h3;
+        } else {
+            v0 = b * g;
+            v1 = v0 + h1;
+            v2 = v0 + h2;
+            v3 = v0 + h3;
         }
+        if (o + 4u <= n)
+            emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, 4u, v0, v1, v2, v3, sh);
+        else if (o < n)
+            emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, n - o, v0, v1, v2, v3, sh);
     }
 }
 
@@ -342,22 +332,11 @@ qmc_status validate_generation(const char* who, qmc_context ctx, const void* tab
     return QMC_OK;
 }
 
-// Grid of the fast kernels.  Contiguous runs: one wavefront per `cpw` chunks.  Interleaved:
-// a power-of-two number of wavefronts (at most tune.waves, at most one per chunk), so that the
-// index stride between a wavefront's chunks is a power of two.
-uint32_t fast_grid(uint64_t n, const GenTune& tn, uint32_t* nchunks, uint32_t* q0) {
+// Grid of the fast kernels: x = runs of cpw chunks, y = dimension (dimension-major dispatch).
+dim3 fast_grid(uint64_t n, uint32_t s, const GenTune& tn, uint32_t* nchunks) {
     *nchunks = static_cast<uint32_t>((n + kChunk - 1) / kChunk);
-    if (!tn.interleaved) {
-        *q0 = 8;
-        const uint32_t waves = (*nchunks + tn.chunks_per_wave - 1) / tn.chunks_per_wave;
-        return (waves + kWavesPerBlock - 1) / kWavesPerBlock;
-    }
-    uint32_t waves = kWavesPerBlock;
-    while (waves * 2 <= tn.waves && waves * 2 <= *nchunks) waves *= 2;
-    uint32_t lg = 0;
-    while ((1u << lg) < waves) ++lg;
-    *q0 = 8 + lg;
-    return waves / kWavesPerBlock;
+    const uint32_t cpw = tn.chunks_per_wave;
+    return dim3((*nchunks + cpw - 1) / cpw, s);
 }
 
 uint32_t general_grid(const qmc_context ctx, uint64_t n) {
@@ -400,13 +379,12 @@ extern "C" qmc_status qmc_generate_sobol(qmc_context ctx, qmc_stream stream, con
                 with_outputs(out_u32 != nullptr, out_f32 != nullptr, [&](auto WU, auto WF) {
                     if (fast) {
                         with_bool(ctx->sobol_tune.nontemporal != 0, [&](auto NT) {
-                            uint32_t nchunks, q0;
+                            uint32_t nchunks;
                             const GenTune& tn = ctx->sobol_tune;
-                            const uint32_t grid = fast_grid(nn, tn, &nchunks, &q0);
+                            const dim3 grid = fast_grid(nn, s, tn, &nchunks);
                             hipLaunchKernelGGL((sobol_fast<NUS.value, SH.value, SX.value, WU.value, WF.value, NT.value>),
-                                               dim3(grid), dim3(kBlock), 0, hs, matrices, s, first32, nn, nus_seeds,
-                                               shifts, out_u32, out_f32, ld, tn.chunks_per_wave, nchunks,
-                                               tn.interleaved, q0);
+                                               grid, dim3(kWave), 0, hs, matrices, first32, nn, nus_seeds, shifts,
+                                               out_u32, out_f32, ld, tn.chunks_per_wave, nchunks);
                         });
                     } else {
                         hipLaunchKernelGGL((sobol_general<NUS.value, SH.value, SX.value, WU.value, WF.value>),
@@ -449,13 +427,13 @@ extern "C" qmc_status qmc_generate_lattice(qmc_context ctx, qmc_stream stream, c
                 with_outputs(out_u32 != nullptr, out_f32 != nullptr, [&](auto WU, auto WF) {
                     if (fast) {
                         with_bool(ctx->lattice_tune.nontemporal != 0, [&](auto NT) {
-                            uint32_t nchunks, q0;
+                            uint32_t nchunks;
                             const GenTune& tn = ctx->lattice_tune;
-                            const uint32_t grid = fast_grid(nn, tn, &nchunks, &q0);
+                            const dim3 grid = fast_grid(nn, s, tn, &nchunks);
                             hipLaunchKernelGGL(
-                                (lattice_fast<BK.value, SH.value, SX.value, WU.value, WF.value, NT.value>),
-                                dim3(grid), dim3(kBlock), 0, hs, generator, s, first32, nn, shifts, out_u32, out_f32,
-                                ld, tn.chunks_per_wave, nchunks, tn.interleaved);
+                                (lattice_fast<BK.value, SH.value, SX.value, WU.value, WF.value, NT.value>), grid,
+                                dim3(kWave), 0, hs, generator, first32, nn, shifts, out_u32, out_f32, ld,
+                                tn.chunks_per_wave, nchunks);
                         });
                     } else {
                         hipLaunchKernelGGL((lattice_general<BK.value, SH.value, SX.value, WU.value, WF.value>),

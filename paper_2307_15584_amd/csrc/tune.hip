@@ -88,10 +88,8 @@ extern "C" qmc_status qmc_autotune_generate(qmc_context ctx, qmc_stream stream, 
     GenTune best = saved;
     float best_ms = 1e30f;
     std::vector<GenTune> cands;
-    for (uint32_t nt = 0; nt < 2; ++nt) {
-        for (uint32_t w : {2048u, 4096u, 8192u, 16384u}) cands.push_back(GenTune{1u, saved.chunks_per_wave, w, nt});
-        for (uint32_t cpw : {1u, 2u, 4u, 8u, 16u, 32u}) cands.push_back(GenTune{0u, cpw, saved.waves, nt});
-    }
+    for (uint32_t nt = 0; nt < 2; ++nt)
+        for (uint32_t cpw : {1u, 2u, 4u, 8u}) cands.push_back(GenTune{cpw, nt});
     for (const GenTune& c : cands) {
         slot = c;
         const float ms = time_ms(hs, 3, run);
@@ -99,9 +97,8 @@ extern "C" qmc_status qmc_autotune_generate(qmc_context ctx, qmc_stream stream, 
             slot = saved;
             return fail(QMC_ERR_DEVICE, "qmc_autotune_generate: candidate failed: %s", last_error_slot().c_str());
         }
-        append(report, report_bytes,
-               "{\"interleaved\":%u,\"chunks_per_wave\":%u,\"waves\":%u,\"nontemporal\":%u,\"ms\":%.5f}\n",
-               c.interleaved, c.chunks_per_wave, c.waves, c.nontemporal, ms);
+        append(report, report_bytes, "{\"chunks_per_wave\":%u,\"nontemporal\":%u,\"ms\":%.5f}\n",
+               c.chunks_per_wave, c.nontemporal, ms);
         if (ms < best_ms) {
             best_ms = ms;
             best = c;
@@ -158,9 +155,8 @@ extern "C" qmc_status qmc_tune_save(qmc_context ctx, const char* path) {
     if (!f) return fail(QMC_ERR_INVALID_ARGUMENT, "qmc_tune_save: cannot open %s", path);
     for (int k = 0; k < 2; ++k) {
         const GenTune& t = k == 0 ? ctx->sobol_tune : ctx->lattice_tune;
-        std::fprintf(f, "%s\"%s\":{\"interleaved\":%u,\"chunks_per_wave\":%u,\"waves\":%u,\"nontemporal\":%u},\n",
-                     k == 0 ? "{" : " ", k == 0 ? "sobol" : "lattice", t.interleaved, t.chunks_per_wave, t.waves,
-                     t.nontemporal);
+        std::fprintf(f, "%s\"%s\":{\"chunks_per_wave\":%u,\"nontemporal\":%u},\n", k == 0 ? "{" : " ",
+                     k == 0 ? "sobol" : "lattice", t.chunks_per_wave, t.nontemporal);
     }
     std::fprintf(f, " \"integrate\":[");
     bool first = true;
@@ -194,14 +190,13 @@ extern "C" qmc_status qmc_tune_load(qmc_context ctx, const char* path) {
         return fail(QMC_ERR_INVALID_ARGUMENT, "qmc_tune_load: not a tuning file");
     for (int k = 0; k < 2; ++k) {
         const size_t at = text.find(k == 0 ? "\"sobol\"" : "\"lattice\"");
-        uint32_t il, cpw, w, nt;
-        if (at == std::string::npos || field(at, "interleaved", &il) == std::string::npos ||
-            field(at, "chunks_per_wave", &cpw) == std::string::npos || field(at, "waves", &w) == std::string::npos ||
+        uint32_t cpw, nt;
+        if (at == std::string::npos || field(at, "chunks_per_wave", &cpw) == std::string::npos ||
             field(at, "nontemporal", &nt) == std::string::npos)
             continue;
-        if (cpw < 1 || cpw > 1024 || w < 4 || w > (1u << 20)) continue;
+        if (cpw < 1 || cpw > 1024) continue;
         GenTune& t = k == 0 ? ctx->sobol_tune : ctx->lattice_tune;
-        t = GenTune{il ? 1u : 0u, cpw, w, nt ? 1u : 0u};
+        t = GenTune{cpw, nt ? 1u : 0u};
     }
     size_t pos = text.find("\"integrate\"");
     while (pos != std::string::npos) {
