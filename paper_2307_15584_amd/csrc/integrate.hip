@@ -514,12 +514,16 @@ __device__ __forceinline__ void load_lobe(const Args& a, uint32_t kg, float (&st
     *lobe = k;
     *own = k < a.L;
     const uint32_t d = a.d, L = a.L;
+    // One base pointer per parameter block, indexed with the unrolled jj: keeps a single 64-bit
+    // address live instead of one per dimension.
+    const float* pc = a.params + (*own ? uint64_t(k) * d + h * LL::DH : 0);
+    const float* pl = pc + uint64_t(L) * d;
 #pragma unroll
     for (int jj = 0; jj < LL::DH; ++jj) {
         const uint32_t j = h * LL::DH + jj;
         if (*own && j < d) {
-            const float c = a.params[k * d + j];
-            const float l = a.params[L * d + k * d + j];
+            const float c = pc[jj];
+            const float l = pl[jj];
             st[jj] = kKappa * expf(-l);
             b[jj] = -c * st[jj];
         } else {
@@ -675,12 +679,13 @@ __device__ __forceinline__ void lobes_bwd_tile(const Args& a, const SamplerLds<D
             [&](uint32_t) {});
         if (own) {
             const uint32_t d = a.d, L = a.L;
+            float* oc = out + uint64_t(lobe) * d + half * LL::DH;
+            float* ol = oc + uint64_t(L) * d;
 #pragma unroll
             for (int jj = 0; jj < LL::DH; ++jj) {
-                const uint32_t j = half * LL::DH + jj;
-                if (j < d) {
-                    out[lobe * d + j] = acc_c[jj] * st[jj];
-                    out[L * d + lobe * d + j] = acc_l[jj];
+                if (half * LL::DH + jj < d) {
+                    oc[jj] = acc_c[jj] * st[jj];
+                    ol[jj] = acc_l[jj];
                 }
             }
             if (half == 0) out[2 * L * d + lobe] = acc_w;
@@ -710,12 +715,12 @@ __global__ __launch_bounds__(kBlock) void lobes_bwd(Args a) {
 // L = (1/P) sum_p (I_p - T_p)^2: the estimate of each pixel, dL/dI_p = 2 (I_p - T_p) / P and
 // the adjoint over the same samples in one kernel.  Partial rows hold [dL/dtheta, loss sum].
 // The adjoint's per-pixel sums  sum_i G,  sum_i w G t_j  and  sum_i w G t_j^2  do not depend on
-// dL/dI_p, only their final scaling does; so when all lobes fit one lane group, a single pass
-// over each pixel's samples accumulates the estimate and these sums together, and at the end of
-// the pixel (a uniform event, as in the forward pass) scales them by dL/dI_p / N_p into the
-// lobe's totals.  Samples are generated once.  With more lobes than one group the estimate needs
-// every group first, so such launches (SINGLE = false) run the forward walk and then the
-// adjoint walk.
+// dL/dI_p, only their final scaling does.  When all lobes fit one lane group (SINGLE), a big
+// pixel's samples are generated once and feed the estimate and these sums together; packed
+// pixels, whose samples share rounds, get their estimates from a forward walk first.  With more
+// lobes than one group the estimate needs every group first, and for d > 8 a lane has no
+// registers left for the unscaled sums, so such launches (SINGLE = false) run the forward walk
+// and then the adjoint walk.
 template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK, bool SINGLE>
 __global__ __launch_bounds__(kBlock) void lobes_step(Args a) {
     using LL = LobeLayout<D>;
@@ -735,73 +740,74 @@ __global__ __launch_bounds__(kBlock) void lobes_step(Args a) {
         const TileInfo ti = tile_info(a, task);
         float* out = a.partials + uint64_t(task) * (a.n_theta + 1);
         if constexpr (SINGLE) {
+            // (1) Packed pixels (fewer than 64 samples): forward sums first, so that their
+            // samples carry a known scale dL/dI_p / N_p through the adjoint walk below.
+            TileInfo ts = ti;
+            ts.n = ti.ns;  // hides the big pixels from this walk
+            lobes_fwd_tile<D, SK, NUS, SHIFT, BACK>(a, S, PX, ST, RES[wv], task, ts);
+            const uint32_t N = ti.inb ? a.counts[ti.p] : 0u;
+            float gs = 0.0f, sq = 0.0f;
+            if (ti.inb && ti.n < kWave) {  // packed or empty pixel
+                const float I = N ? RES[wv][lane] / static_cast<float>(N) : 0.0f;
+                const float diff = I - a.target[ti.p];
+                if (a.means) a.means[ti.p] = I;
+                sq = diff * diff;
+                gs = N ? 2.0f * diff * invP / static_cast<float>(N) : 0.0f;
+            }
+            float loss = wave_sum(sq);
+            wave_sync();
+            // (2) One walk over every sample.  A big pixel's rounds hold only its own samples:
+            // its estimate and the unscaled adjoint sums  sum_i G,  sum_i w G t_j,
+            // sum_i w G t_j^2  accumulate together, and at the end of the pixel the sums are
+            // scaled by dL/dI_p / N_p into the lobe's totals.  Packed samples enter the same
+            // sums already scaled.  No pixel bookkeeping runs inside the per-sample loop.
             float st[LL::DH], b[LL::DH], w;
             uint32_t lobe;
             bool own;
             load_lobe<D>(a, 0, st, b, &w, &lobe, &own);
-            const float wf = half == 0 ? w : 0.0f;  // both halves form G; one adds it to sums
-            float acc_c[LL::DH], acc_l[LL::DH], acc_w = 0.0f, loss = 0.0f;
-            float pf = 0.0f, pw = 0.0f, pc[LL::DH], pl[LL::DH];  // the current pixel's sums
+            const float wf = half == 0 ? w : 0.0f;  // both halves form G; one adds it to the estimate
+            // The lobe's running totals live in LDS (touched once per pixel).
+            __shared__ float ACC[kWavesPerBlock][2 * LL::DH + 1][kWave];
+            float(&acc)[2 * LL::DH + 1][kWave] = ACC[wv];
 #pragma unroll
-            for (int jj = 0; jj < LL::DH; ++jj) acc_c[jj] = acc_l[jj] = pc[jj] = pl[jj] = 0.0f;
-            uint32_t cur = 0xFFFFFFFFu;
-            auto flush = [&]() {
-                if (cur != 0xFFFFFFFFu) {
-                    const uint32_t pp = task * kTile + cur;
-                    const uint32_t N = a.counts[pp];
-                    const float I = wave_sum(pf) / static_cast<float>(N);
-                    const float diff = I - a.target[pp];
-                    if (lane == 0) {
-                        if (a.means) a.means[pp] = I;
-                        loss = fmaf(diff, diff, loss);
-                    }
-                    const float scale = 2.0f * diff * invP / static_cast<float>(N);
-                    acc_w = fmaf(scale, pw, acc_w);
+            for (int k = 0; k < 2 * LL::DH + 1; ++k) acc[k][lane] = 0.0f;
+            float pf = 0.0f, pw = 0.0f, pc[LL::DH], pl[LL::DH];
 #pragma unroll
-                    for (int jj = 0; jj < LL::DH; ++jj) {
-                        acc_c[jj] = fmaf(scale, pc[jj], acc_c[jj]);
-                        acc_l[jj] = fmaf(scale, pl[jj], acc_l[jj]);
-                    }
+            for (int jj = 0; jj < LL::DH; ++jj) pc[jj] = pl[jj] = 0.0f;
+            auto add_sums = [&](float scale) {
+                acc[2 * LL::DH][lane] = fmaf(scale, pw, acc[2 * LL::DH][lane]);
+#pragma unroll
+                for (int jj = 0; jj < LL::DH; ++jj) {
+                    acc[jj][lane] = fmaf(scale, pc[jj], acc[jj][lane]);
+                    acc[LL::DH + jj][lane] = fmaf(scale, pl[jj], acc[LL::DH + jj][lane]);
                 }
                 pf = pw = 0.0f;
 #pragma unroll
                 for (int jj = 0; jj < LL::DH; ++jj) pc[jj] = pl[jj] = 0.0f;
             };
-            // pixels with an empty window still get a mean (0) and their loss term
-            if (ti.inb && ti.n == 0) {
-                const float diff = 0.0f - a.target[ti.p];
-                if (a.means) a.means[ti.p] = 0.0f;
-                RES[wv][lane] = diff * diff;
-            } else {
-                RES[wv][lane] = 0.0f;
-            }
             walk_tile<D, SK, NUS, SHIFT, BACK, true>(
                 a, S, PX, task, ti.n, ti.inb, ti.off, ti.total, [&](uint32_t) {},
-                [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t, bool, uint32_t, uint32_t) {
+                [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t, bool is_big, uint32_t, uint32_t) {
                     constexpr uint32_t R = StageLds<D>::kRows;
+                    const float sc = is_big ? 1.0f : __shfl(gs, q, kWave);
                     for (uint32_t r0 = 0; r0 < count; r0 += R) {
                         if (lane >= r0 && lane < r0 + R) {
 #pragma unroll
                             for (int j = 0; j < D; ++j) ST.y[lane - r0][j] = x[j];
-                            ST.q[lane - r0] = q;
+                            ST.scale[lane - r0] = sc;
                         }
                         wave_sync();
                         const uint32_t mend = min(count - r0, R);
-#pragma nounroll
                         for (uint32_t m = 0; m < mend; ++m) {
-                            const uint32_t qm = __builtin_amdgcn_readfirstlane(ST.q[m]);
-                            if (qm != cur) {
-                                flush();
-                                cur = qm;
-                            }
                             float t[LL::DH];
                             const float G = exp2_neg(lobe_exponent<D>(ST, m, st, b, t));
-                            const float wG = w * G;
+                            const float g = ST.scale[m] * G;
                             pf = fmaf(wf, G, pf);
-                            pw += G;
+                            pw += g;
+                            const float wg = w * g;
 #pragma unroll
                             for (int jj = 0; jj < LL::DH; ++jj) {
-                                const float gt = wG * t[jj];
+                                const float gt = wg * t[jj];
                                 pc[jj] += gt;
                                 pl[jj] = fmaf(gt, t[jj], pl[jj]);
                             }
@@ -809,22 +815,30 @@ __global__ __launch_bounds__(kBlock) void lobes_step(Args a) {
                         wave_sync();
                     }
                 },
-                [&](uint32_t) {});
-            flush();
+                [&](uint32_t q) {
+                    const uint32_t pp = task * kTile + q;
+                    const uint32_t Nq = a.counts[pp];  // >= 64
+                    const float I = wave_sum(pf) / static_cast<float>(Nq);
+                    const float diff = I - a.target[pp];
+                    if (lane == 0 && a.means) a.means[pp] = I;
+                    loss = fmaf(diff, diff, loss);
+                    add_sums(2.0f * diff * invP / static_cast<float>(Nq));
+                });
+            add_sums(1.0f);  // packed samples: already scaled
             if (own) {
                 const uint32_t d = a.d, L = a.L;
+                float* oc = out + uint64_t(lobe) * d + half * LL::DH;
+                float* ol = oc + uint64_t(L) * d;
 #pragma unroll
                 for (int jj = 0; jj < LL::DH; ++jj) {
-                    const uint32_t j = half * LL::DH + jj;
-                    if (j < d) {
-                        out[lobe * d + j] = acc_c[jj] * st[jj];
-                        out[L * d + lobe * d + j] = acc_l[jj];
+                    if (half * LL::DH + jj < d) {
+                        oc[jj] = acc[jj][lane] * st[jj];
+                        ol[jj] = acc[LL::DH + jj][lane];
                     }
                 }
-                if (half == 0) out[2 * L * d + lobe] = acc_w;
+                if (half == 0) out[2 * L * d + lobe] = acc[2 * LL::DH][lane];
             }
-            const float empty_loss = wave_sum(RES[wv][lane]);
-            if (lane == 0) out[a.n_theta] = loss + empty_loss;
+            if (lane == 0) out[a.n_theta] = loss;
             wave_sync();
         } else {
             // forward walk over every lobe group, per-pixel loss gradient, adjoint walk
@@ -1176,10 +1190,9 @@ qmc_status integrate_common(const char* who, qmc_context ctx, qmc_stream stream,
             else
                 dispatch_sampler<LobesStepFam<8, false>>(sp->kind, nus, shift, back, grid, hs, a);
         } else {
-            if (ig->num_lobes <= LobeLayout<64>::LPG)
-                dispatch_sampler<LobesStepFam<64, true>>(sp->kind, nus, shift, back, grid, hs, a);
-            else
-                dispatch_sampler<LobesStepFam<64, false>>(sp->kind, nus, shift, back, grid, hs, a);
+            // d > 8: a lane's share of the adjoint state (32 dimensions) leaves no registers for
+            // a pixel's unscaled sums, so the step runs the forward walk, then the adjoint walk.
+            dispatch_sampler<LobesStepFam<64, false>>(sp->kind, nus, shift, back, grid, hs, a);
         }
         double* chunk_sums = reinterpret_cast<double*>(static_cast<char*>(ws) + pl.chunks_off);
         hipLaunchKernelGGL(reduce_partials_chunks, dim3((pl.n_row + 63) / 64, pl.num_chunks), dim3(256), 0, hs,

@@ -342,7 +342,8 @@ def test_integration_argument_errors(qmc):
                                            (64, 32, 6, 4, "64"), (5, 7, 13, 4, "edge")])
 def test_fused_l2_step_matches_oracle(qmc, d, L, W, H, cname):
     """The fused forward + L2 gradient + adjoint kernel: loss, means and dL/dtheta against
-    the FP64 oracle (the 64-spp tiles take the register-reuse path, the others two passes)."""
+    the FP64 oracle: one walk per tile (d <= 8, one lane group) with big pixels only and with
+    packed, empty and big pixels mixed, and the two-walk variant (more lobes than lanes, d = 64)."""
     import torch
 
     P = W * H
