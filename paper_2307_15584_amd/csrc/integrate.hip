@@ -199,58 +199,76 @@ __device__ void stage_sampler(SamplerLds<D>& S, const Args& a) {
     }
 }
 
+// Dimensions of a sample generated by one lane: all of them for d <= 32; for d > 32 two lanes
+// (l and l + 32) share a sample, each forming one half, so that a lane never holds 64
+// coordinates at once.
+template <int D>
+constexpr int kGen = D > 32 ? 32 : D;
+
+// First dimension this lane generates.
+template <int D>
+__device__ __forceinline__ uint32_t gen_first_dim() {
+    if constexpr (D > 32)
+        return (lane_id() >> 5) * 32u;
+    else
+        return 0u;
+}
+
 // Per-dimension Sobol' index part of sample i.  With a per-round base (windows starting on a
 // multiple of 64) it is base[j] ^ T[j][k], k = i - begin < 64; otherwise the plain matrix
 // product C_j i is formed, looping over index bits outside and dimensions inside so that
 // the per-dimension values stay in registers.  Mirrored when scrambling.
 template <int D, bool NUS>
-__device__ __forceinline__ void index_part(uint32_t (&v)[D], const SamplerLds<D>& S, const Args& a, uint32_t i,
-                                           uint32_t k, const uint32_t* base) {
+__device__ __forceinline__ void index_part(uint32_t (&v)[kGen<D>], const SamplerLds<D>& S, const Args& a, uint32_t i,
+                                           uint32_t k, const uint32_t* base, uint32_t j0) {
+    constexpr int G = kGen<D>;
     if (base) {
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = base[j] ^ S.T[j][k];
+        for (int jj = 0; jj < G; ++jj) v[jj] = base[j0 + jj] ^ S.T[j0 + jj][k];
     } else {
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = 0u;
+        for (int jj = 0; jj < G; ++jj) v[jj] = 0u;
         for (uint32_t b = 0; b < 32; ++b) {
             if ((i >> b) & 1u) {
 #pragma unroll
-                for (int j = 0; j < D; ++j)
-                    if (uint32_t(j) < a.d) v[j] ^= a.table[j * 32 + b];
+                for (int jj = 0; jj < G; ++jj)
+                    if (j0 + jj < a.d) v[jj] ^= a.table[(j0 + jj) * 32 + b];
             }
         }
         if constexpr (NUS) {
 #pragma unroll
-            for (int j = 0; j < D; ++j) v[j] = dev::brev(v[j]);
+            for (int jj = 0; jj < G; ++jj) v[jj] = dev::brev(v[jj]);
         }
     }
 }
 
-// Components j < d of sample i of pixel p into x (x[j] = 0 for j >= d).
+// Components j0 + jj < d (jj < kGen<D>) of sample i of pixel p into x (0 beyond d).
 //   base:   per-round index part in LDS (PixelLds::B or SamplerLds::B0); with it, the Sobol'
-//           index part is base[j] ^ T[j][k] for k = i - begin < 64.  NULL: C_j i directly.
+//           index part is base[j] ^ T[j][k] for k = i - begin mod 64.  NULL: C_j i directly.
 //   PX:     per-pixel values of a big pixel (NULL: derive them from the hash per lane);
 //   valid:  false for lanes past the end of a window, which must not read materialised samples.
 template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK>
-__device__ __forceinline__ void sample_point(float (&x)[D], const SamplerLds<D>& S, const PixelLds<D>* PX,
+__device__ __forceinline__ void sample_point(float (&x)[kGen<D>], const SamplerLds<D>& S, const PixelLds<D>* PX,
                                              const Args& a, uint32_t p, uint32_t i, uint32_t k,
-                                             const uint32_t* base, bool valid) {
+                                             const uint32_t* base, bool valid, uint32_t j0) {
+    constexpr int G = kGen<D>;
     if constexpr (SK == QMC_SAMPLER_POINTS) {
         const uint64_t off = valid ? a.offsets[p] + i : 0;
 #pragma unroll
-        for (int j = 0; j < D; ++j)
-            x[j] = (valid && uint32_t(j) < a.d) ? a.points[uint64_t(j) * a.points_ld + off] : 0.0f;
+        for (int jj = 0; jj < G; ++jj)
+            x[jj] = (valid && j0 + jj < a.d) ? a.points[uint64_t(j0 + jj) * a.points_ld + off] : 0.0f;
     } else {
-        uint32_t ip[D];
-        if constexpr (SK == QMC_SAMPLER_SOBOL) index_part<D, NUS>(ip, S, a, i, k, base);
+        uint32_t ip[G];
+        if constexpr (SK == QMC_SAMPLER_SOBOL) index_part<D, NUS>(ip, S, a, i, k, base, j0);
         const uint32_t bi = (SK == QMC_SAMPLER_LATTICE) ? dev::brev(BACK ? ~i : i) : 0u;
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            x[j] = 0.0f;
-            if (uint32_t(j) < a.d) {
+        for (int jj = 0; jj < G; ++jj) {
+            const uint32_t j = j0 + jj;
+            x[jj] = 0.0f;
+            if (j < a.d) {
                 uint32_t v;
                 if constexpr (SK == QMC_SAMPLER_SOBOL)
-                    v = ip[j];
+                    v = ip[jj];
                 else
                     v = bi * S.g[j];
                 if constexpr (NUS) {
@@ -268,7 +286,7 @@ __device__ __forceinline__ void sample_point(float (&x)[D], const SamplerLds<D>&
                     const uint32_t sh = PX ? PX->shift[j] : dev::pcg_hash(S.kc[j] ^ p);
                     v = a.sxor ? (v ^ sh) : (v + sh);
                 }
-                x[j] = dev::u32_to_unifloat(v);
+                x[jj] = dev::u32_to_unifloat(v);
             }
         }
     }
@@ -276,12 +294,19 @@ __device__ __forceinline__ void sample_point(float (&x)[D], const SamplerLds<D>&
 
 // ------------------------------------------------------------- tile walker ----
 //
-// Visits every sample of the tile's window in rounds of at most 64 (one per lane; the valid
-// lanes of a round are the prefix lane < count).  Calls, in order:
+// Samples handed to one on_round call: 64 (one per lane), or 32 for d > 32, where lanes l and
+// l + 32 form the two halves of sample l.
+template <int D>
+constexpr uint32_t kRoundSamples = D > 32 ? 32u : kWave;
+
+// Visits every sample of the tile's window in rounds of at most kRoundSamples<D>; the valid
+// samples of a round are the prefix r < count, r = lane % kRoundSamples<D>.  Calls, in order:
 //   on_big_begin(q)                                 before the rounds of big pixel q;
-//   on_round(x, count, q, p, is_big, slot0, i)      for each round (x: this lane's sample,
-//                                                   q/p: its pixel in the tile / image,
-//                                                   slot0: packed slot of lane 0, i: its index);
+//   on_round(x, count, q, p, is_big, slot0, i)      for each round (x: this lane's part of
+//                                                   its sample, dimensions gen_first_dim() +
+//                                                   [0, kGen<D>); q/p: the sample's pixel in
+//                                                   the tile / image; slot0: packed slot of
+//                                                   sample 0; i: the sample's index);
 //   on_big_end(q)                                   after the rounds of big pixel q.
 // Packed pixels follow the big ones, in pixel order.  With DELTA the per-pixel integrand
 // offsets are added (y = x + delta, rounded to binary32).
@@ -290,7 +315,11 @@ template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK, bool DELTA, typen
 __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S, PixelLds<D>& PX, uint32_t task,
                                           uint32_t n, bool inb, uint32_t off, uint32_t total_small,
                                           BigBegin&& on_big_begin, Round&& on_round, BigEnd&& on_big_end) {
+    constexpr int G = kGen<D>;
+    constexpr uint32_t RS = kRoundSamples<D>;
     const uint32_t lane = lane_id();
+    const uint32_t row = RS == kWave ? lane : lane % RS;
+    const uint32_t j0 = gen_first_dim<D>();
     const uint32_t p0 = task * kTile;
     uint64_t bigmask = __ballot(inb && n >= kWave);
     while (bigmask) {
@@ -310,18 +339,30 @@ __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S,
         }
         wave_sync();
         on_big_begin(q);
-        const uint32_t rounds = (nn + kWave - 1) / kWave;
+        const uint32_t rounds = (nn + kWave - 1) / kWave;  // blocks of 64 indices
         for (uint32_t r = 0; r < rounds; ++r) {
-            const uint32_t k = r * kWave + lane;
-            const uint32_t count = min(nn - r * kWave, kWave);
-            float x[D];
-            sample_point<D, SK, NUS, SHIFT, BACK>(x, S, &PX, a, pp, a.begin + k, lane, a.aligned ? PX.B : nullptr,
-                                                  lane < count);
-            if constexpr (DELTA) {
+            // One call per 64 indices, or two (halves of 32 samples) for d > 32; both use the
+            // round's index part B, with k & 63 selecting the T entry.
+            auto visit = [&](uint32_t kb, uint32_t count, uint32_t t_index) {
+                const uint32_t k = kb + row;
+                float x[G];
+                sample_point<D, SK, NUS, SHIFT, BACK>(x, S, &PX, a, pp, a.begin + k, t_index,
+                                                      a.aligned ? PX.B : nullptr, row < count, j0);
+                if constexpr (DELTA) {
 #pragma unroll
-                for (int j = 0; j < D; ++j) x[j] = uint32_t(j) < a.d ? x[j] + PX.delta[j] : 0.0f;
+                    for (int jj = 0; jj < G; ++jj) x[jj] = j0 + jj < a.d ? x[jj] + PX.delta[j0 + jj] : 0.0f;
+                }
+                on_round(x, count, q, pp, true, 0u, a.begin + k);
+            };
+            if constexpr (RS == kWave) {
+                visit(r * kWave, min(nn - r * kWave, kWave), lane);
+            } else {
+                for (uint32_t part = 0; part < kWave / RS; ++part) {
+                    const uint32_t kb = r * kWave + part * RS;
+                    if (kb >= nn) break;
+                    visit(kb, min(nn - kb, RS), part * RS + row);
+                }
             }
-            on_round(x, count, q, pp, true, 0u, a.begin + k);
             if constexpr (SK == QMC_SAMPLER_SOBOL) {
                 if (a.aligned && r + 1 < rounds) {
                     const uint32_t h = (a.begin >> 6) + r;
@@ -336,23 +377,24 @@ __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S,
         wave_sync();
     }
 
-    for (uint32_t slot0 = 0; slot0 < total_small; slot0 += kWave) {
-        const uint32_t g = slot0 + lane;
-        const uint32_t count = min(total_small - slot0, kWave);
-        const bool valid = lane < count;
+    for (uint32_t sb = 0; sb < total_small; sb += RS) {
+        const uint32_t g = sb + row;
+        const uint32_t count = min(total_small - sb, RS);
+        const bool valid = row < count;
         const uint32_t qo = packed_owner(off, g);
         const uint32_t offq = __shfl(off, qo, kWave);
         const uint32_t q = valid ? qo : 0u;
         const uint32_t pp = p0 + q;
         const uint32_t k = valid ? g - offq : 0u;
-        float x[D];
+        float x[G];
         sample_point<D, SK, NUS, SHIFT, BACK>(x, S, nullptr, a, pp, a.begin + k, k & (kWave - 1),
-                                              a.aligned ? S.B0 : nullptr, valid);
+                                              a.aligned ? S.B0 : nullptr, valid, j0);
         if constexpr (DELTA) {
 #pragma unroll
-            for (int j = 0; j < D; ++j) x[j] = uint32_t(j) < a.d ? x[j] + pixel_delta(S.kd[j], pp) : 0.0f;
+            for (int jj = 0; jj < G; ++jj)
+                x[jj] = j0 + jj < a.d ? x[jj] + pixel_delta(S.kd[j0 + jj], pp) : 0.0f;
         }
-        on_round(x, count, q, pp, false, slot0, a.begin + k);
+        on_round(x, count, q, pp, false, sb, a.begin + k);
     }
 }
 
@@ -492,8 +534,7 @@ struct LobeLayout {
     static constexpr uint32_t LPG = kWave / H;
 };
 
-// Staged samples of one round.  For d > 32 a round is staged in two passes of 32 samples,
-// which halves the LDS footprint so that two blocks fit on a compute unit.
+// Staged samples of one round (kRoundSamples<D> rows).
 template <int D>
 struct StageLds {
     static constexpr uint32_t kRows = D > 32 ? 32 : kWave;
@@ -501,6 +542,17 @@ struct StageLds {
     float scale[kRows];                 // adjoint weight of the sample (gI_p / N_p)
     uint32_t q[kRows];                  // tile-local pixel of the sample
 };
+
+// Writes this lane's part of its sample into row lane % kRows (rows r < count are valid).
+template <int D>
+__device__ __forceinline__ void stage_rows(StageLds<D>& ST, const float (&x)[kGen<D>], uint32_t count) {
+    const uint32_t r = lane_id() % StageLds<D>::kRows;
+    const uint32_t j0 = gen_first_dim<D>();
+    if (r < count) {
+#pragma unroll
+        for (int jj = 0; jj < kGen<D>; ++jj) ST.y[r][j0 + jj] = x[jj];
+    }
+}
 
 // Loads this lane's lobe parameters for group kg: st = kKappa e^-l, b = -c st (zero when the
 // lane owns no lobe or the dimension is unused, so those terms vanish).
@@ -548,7 +600,11 @@ __device__ __forceinline__ float lobe_exponent(const StageLds<D>& ST, uint32_t m
         t[jj] = fmaf(y[jj], st[jj], b[jj]);
         e = fmaf(t[jj], t[jj], e);
     }
-    if constexpr (LL::H == 2) e += __shfl_xor(e, 32, kWave);
+    if constexpr (LL::H == 2) {
+        // Both halves of the sum in every lane (v_permlane32_swap: no LDS round trip).
+        const auto h2 = __builtin_amdgcn_permlane32_swap(__float_as_uint(e), __float_as_uint(e), false, false);
+        e = __uint_as_float(h2[0]) + __uint_as_float(h2[1]);
+    }
     return e;
 }
 
@@ -581,17 +637,25 @@ __device__ __forceinline__ void lobes_fwd_tile(const Args& a, const SamplerLds<D
         };
         walk_tile<D, SK, NUS, SHIFT, BACK, true>(
             a, S, PX, task, ti.n, ti.inb, ti.off, ti.total, [&](uint32_t) {},
-            [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t, bool, uint32_t, uint32_t) {
-                constexpr uint32_t R = StageLds<D>::kRows;
-                for (uint32_t r0 = 0; r0 < count; r0 += R) {
-                    if (lane >= r0 && lane < r0 + R) {
-#pragma unroll
-                        for (int j = 0; j < D; ++j) ST.y[lane - r0][j] = x[j];
-                        ST.q[lane - r0] = q;
+            [&](const float (&x)[kGen<D>], uint32_t count, uint32_t q, uint32_t, bool is_big, uint32_t, uint32_t) {
+                stage_rows<D>(ST, x, count);
+                if (lane < count) ST.q[lane] = q;
+                wave_sync();
+                if (is_big) {
+                    // The whole round belongs to pixel q: no per-sample bookkeeping, and two
+                    // samples per iteration for independent work between the dependent steps.
+                    const uint32_t qb = __builtin_amdgcn_readfirstlane(q);
+                    if (qb != cur) {
+                        flush();
+                        cur = qb;
                     }
-                    wave_sync();
-                    const uint32_t mend = min(count - r0, R);
-                    for (uint32_t m = 0; m < mend; ++m) {
+#pragma unroll 2
+                    for (uint32_t m = 0; m < count; ++m) {
+                        float t[LL::DH];
+                        acc = fmaf(w, exp2_neg(lobe_exponent<D>(ST, m, st, b, t)), acc);
+                    }
+                } else {
+                    for (uint32_t m = 0; m < count; ++m) {
                         const uint32_t qm = __builtin_amdgcn_readfirstlane(ST.q[m]);  // same for all lanes
                         if (qm != cur) {
                             flush();
@@ -601,8 +665,8 @@ __device__ __forceinline__ void lobes_fwd_tile(const Args& a, const SamplerLds<D
                         const float e = lobe_exponent<D>(ST, m, st, b, t);
                         acc = fmaf(w, exp2_neg(e), acc);
                     }
-                    wave_sync();
                 }
+                wave_sync();
             },
             [&](uint32_t) {});
         flush();
@@ -649,28 +713,37 @@ __device__ __forceinline__ void lobes_bwd_tile(const Args& a, const SamplerLds<D
         for (int jj = 0; jj < LL::DH; ++jj) acc_c[jj] = acc_l[jj] = 0.0f;
         walk_tile<D, SK, NUS, SHIFT, BACK, true>(
             a, S, PX, task, ti.n, ti.inb, ti.off, ti.total, [&](uint32_t) {},
-            [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t, bool, uint32_t, uint32_t) {
-                constexpr uint32_t R = StageLds<D>::kRows;
+            [&](const float (&x)[kGen<D>], uint32_t count, uint32_t q, uint32_t, bool, uint32_t, uint32_t) {
                 const float sc = __shfl(gscale, q, kWave);
-                for (uint32_t r0 = 0; r0 < count; r0 += R) {
-                    if (lane >= r0 && lane < r0 + R) {
-#pragma unroll
-                        for (int j = 0; j < D; ++j) ST.y[lane - r0][j] = x[j];
-                        ST.scale[lane - r0] = sc;
-                    }
-                    wave_sync();
-                    const uint32_t mend = min(count - r0, R);
-                    for (uint32_t m = 0; m < mend; ++m) {
+                stage_rows<D>(ST, x, count);
+                if (lane < count) ST.scale[lane] = sc;
+                wave_sync();
+                {
+#pragma unroll 2
+                    for (uint32_t m = 0; m < count; ++m) {
                         float t[LL::DH];
                         const float e = lobe_exponent<D>(ST, m, st, b, t);
                         const float aG = ST.scale[m] * exp2_neg(e);
                         acc_w += aG;
                         const float gw = aG * w;
+                        if constexpr (D > 32) {
+                            // 32 dimensions per lane: t is formed again from the staged sample
+                            // rather than kept, which frees 32 registers (two waves per SIMD).
+                            const float* y = &ST.y[m][half * LL::DH];
 #pragma unroll
-                        for (int jj = 0; jj < LL::DH; ++jj) {
-                            const float gt = gw * t[jj];
-                            acc_c[jj] += gt;
-                            acc_l[jj] = fmaf(gt, t[jj], acc_l[jj]);
+                            for (int jj = 0; jj < LL::DH; ++jj) {
+                                const float tj = fmaf(y[jj], st[jj], b[jj]);
+                                const float gt = gw * tj;
+                                acc_c[jj] += gt;
+                                acc_l[jj] = fmaf(gt, tj, acc_l[jj]);
+                            }
+                        } else {
+#pragma unroll
+                            for (int jj = 0; jj < LL::DH; ++jj) {
+                                const float gt = gw * t[jj];
+                                acc_c[jj] += gt;
+                                acc_l[jj] = fmaf(gt, t[jj], acc_l[jj]);
+                            }
                         }
                     }
                     wave_sync();
@@ -787,18 +860,14 @@ __global__ __launch_bounds__(kBlock) void lobes_step(Args a) {
             };
             walk_tile<D, SK, NUS, SHIFT, BACK, true>(
                 a, S, PX, task, ti.n, ti.inb, ti.off, ti.total, [&](uint32_t) {},
-                [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t, bool is_big, uint32_t, uint32_t) {
-                    constexpr uint32_t R = StageLds<D>::kRows;
+                [&](const float (&x)[kGen<D>], uint32_t count, uint32_t q, uint32_t, bool is_big, uint32_t, uint32_t) {
                     const float sc = is_big ? 1.0f : __shfl(gs, q, kWave);
-                    for (uint32_t r0 = 0; r0 < count; r0 += R) {
-                        if (lane >= r0 && lane < r0 + R) {
-#pragma unroll
-                            for (int j = 0; j < D; ++j) ST.y[lane - r0][j] = x[j];
-                            ST.scale[lane - r0] = sc;
-                        }
-                        wave_sync();
-                        const uint32_t mend = min(count - r0, R);
-                        for (uint32_t m = 0; m < mend; ++m) {
+                    stage_rows<D>(ST, x, count);
+                    if (lane < count) ST.scale[lane] = sc;
+                    wave_sync();
+                    {
+#pragma unroll 2
+                        for (uint32_t m = 0; m < count; ++m) {
                             float t[LL::DH];
                             const float G = exp2_neg(lobe_exponent<D>(ST, m, st, b, t));
                             const float g = ST.scale[m] * G;
@@ -917,12 +986,13 @@ __global__ __launch_bounds__(kBlock) void pixel_samples(Args a) {
         const TileInfo ti = tile_info(a, task);
         walk_tile<D, SK, NUS, SHIFT, BACK, false>(
             a, S, PX, task, ti.n, ti.inb, ti.off, ti.total, [&](uint32_t) {},
-            [&](const float (&x)[D], uint32_t count, uint32_t, uint32_t pp, bool, uint32_t, uint32_t i) {
-                if (lane < count) {
+            [&](const float (&x)[kGen<D>], uint32_t count, uint32_t, uint32_t pp, bool, uint32_t, uint32_t i) {
+                if (lane % kRoundSamples<D> < count) {
                     const uint64_t off = a.offsets[pp] + i;
+                    const uint32_t j0 = gen_first_dim<D>();
 #pragma unroll
-                    for (int j = 0; j < D; ++j)
-                        if (uint32_t(j) < a.d) a.out[uint64_t(j) * a.out_ld + off] = x[j];
+                    for (int jj = 0; jj < kGen<D>; ++jj)
+                        if (j0 + jj < a.d) a.out[uint64_t(j0 + jj) * a.out_ld + off] = x[jj];
                 }
             },
             [&](uint32_t) {});
