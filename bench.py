@@ -99,6 +99,31 @@ def _timed(torch, fn, reps, warmup=1):
     return (time.perf_counter() - t0) * 1e3 / reps
 
 
+# ALU roofline of the fused pixel kernels.  One lane-op = one 32-bit VALU operation on one lane;
+# the fp32 vector peak (157.3 TFLOP/s, an FMA counted as 2) is 78.6 T lane-ops/s.
+VALU_PEAK_T = 78.6
+GEN_OPS_PER_DIM = 20      # index part 1, nested scramble 11, rotation 1, conversion 7
+GENZ_EVAL_OPS = 21        # Gaussian 12, phase 4, range reduction 2, exp2 + cos + product 3
+
+
+def lobe_fwd_ops(d, L):
+    """Algorithmic lane-ops per sample of the lobe estimate: generation + offset, then per lobe
+    2 per dimension (t = y s + b, E += t^2), exp2 and the weighted sum."""
+    return d * (GEN_OPS_PER_DIM + 1) + L * (2 * d + 2)
+
+
+def lobe_step_ops(d, L):
+    """Per sample of the fused estimate + adjoint: per lobe 5 per dimension (t, E, and the three
+    adjoint terms) plus exp2, scale, estimate, weight sum and weight product."""
+    return d * (GEN_OPS_PER_DIM + 1) + L * (5 * d + 5)
+
+
+def alu_roofline(samples, ops_per_sample, ms):
+    achieved = samples * ops_per_sample / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 2), "peak": VALU_PEAK_T, "unit": "T lane-ops/s",
+            "frac": round(achieved / VALU_PEAK_T, 4), "ops_per_sample": ops_per_sample}
+
+
 def fill_bandwidth(torch, nbytes=4 << 30, reps=10):
     """Achievable store-only bandwidth (GB/s) of a plain fill of nbytes."""
     buf = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -142,7 +167,8 @@ def pixel_workloads(torch, q, reps, progressive):
         "pixel_samples": n3, "fused_ms": round(fused3, 4), "plain_ms": round(plain_ms3, 4),
         "fused_pixel_samples_per_s": round(n3 / (fused3 * 1e-3), 1),
         "plain_pixel_samples_per_s": round(n3 / (plain_ms3 * 1e-3), 1),
-        "speedup_vs_plain": round(plain_ms3 / fused3, 3)}
+        "speedup_vs_plain": round(plain_ms3 / fused3, 3),
+        "roofline": alu_roofline(n3, 8 * GEN_OPS_PER_DIM + GENZ_EVAL_OPS, fused3)}
     del pts3
 
     # Gaussian lobes, forward + L2 gradient + adjoint
@@ -201,6 +227,8 @@ def pixel_workloads(torch, q, reps, progressive):
         "fused_fwd_bwd_pixel_samples_per_s": round(n4 / (fused4 * 1e-3), 1),
         "plain_fwd_bwd_pixel_samples_per_s": round(n4 / (plain_step_ms * 1e-3), 1),
         "speedup_vs_plain": round(plain_step_ms / fused4, 3),
+        "roofline": alu_roofline(n4, lobe_step_ops(d, L), fused4),
+        "roofline_fwd": alu_roofline(n4, lobe_fwd_ops(d, L), fwd_only),
         "note": "fused: one kernel samples each pixel once and forms the estimate, the L2 loss gradient and the "
                 "adjoint; plain: the samples are materialised in HBM first and the same kernel reads them"}
     del pts4
@@ -228,7 +256,8 @@ def pixel_workloads(torch, q, reps, progressive):
             g_ms = _timed(torch, lambda: run(True), 1)
             e_ms = _timed(torch, lambda: run(False), 1)
             rec[name] = {"graph_ms": round(g_ms, 3), "eager_ms": round(e_ms, 3),
-                         "pixel_samples_per_s": round(n5 / (g_ms * 1e-3), 1)}
+                         "pixel_samples_per_s": round(n5 / (g_ms * 1e-3), 1),
+                         "roofline": alu_roofline(n5, lobe_fwd_ops(d5, L5), g_ms)}
         gm5 = torch.full((P5,), 1e-8, dtype=torch.float32, device="cuda")
         g5 = torch.zeros(th5.numel(), dtype=torch.float32, device="cuda")
         wsb5 = torch.empty(q.qmc_workspace_size(samplers["sobol"], ig5, W5, H5, True), dtype=torch.uint8,
@@ -236,6 +265,7 @@ def pixel_workloads(torch, q, reps, progressive):
         b_ms = _timed(torch, lambda: q.qmc_integrate_pixels_backward(samplers["sobol"], ig5, W5, H5, dc5, gm5, g5,
                                                                      workspace=wsb5), 1)
         rec["sobol"]["backward_ms"] = round(b_ms, 3)
+        rec["sobol"]["backward_roofline"] = alu_roofline(n5, lobe_step_ops(d5, L5), b_ms)
         out["progressive_3840x2160_d64"] = rec
     return out
 
@@ -263,10 +293,12 @@ def pmc_probe(torch, q):
 
 def pmc_probe_pixels(torch, q):
     """One launch each of the fused pixel kernels on the benchmark workloads (default launch
-    shapes), for VALU counter runs."""
+    shapes), for VALU counter runs: Genz forward; lobes d = 8 forward, adjoint and fused L2 step;
+    lobes d = 64 forward and adjoint over one 64-spp window of the 3840x2160 image."""
     import numpy as np
 
-    from synth import counts_pow2, counts_uniform, genz_params, lobe_params, sobol_direction_init
+    from synth import counts_pow2, counts_progressive, counts_uniform, genz_params, lobe_params
+    from synth import sobol_direction_init
 
     W, H = 1920, 1080
     P = W * H
@@ -276,13 +308,22 @@ def pmc_probe_pixels(torch, q):
     dc4 = torch.from_numpy(counts_uniform(W, H, 64).view(np.int32)).cuda()
     ig4 = q.PixelIntegrand.lobes(torch.from_numpy(lobe_params(64, 8, 6)).cuda(), 64, 8, 9)
     gm = torch.full((P,), 1e-7, dtype=torch.float32, device="cuda")
+    target = torch.rand(P, device="cuda")
+    W5, H5 = 3840, 2160
+    dc5 = torch.from_numpy(counts_progressive(W5, H5, 5, passes=16, spp_per_pass=64).view(np.int32)).cuda()
+    ig5 = q.PixelIntegrand.lobes(torch.from_numpy(lobe_params(32, 64, 6)).cuda(), 32, 64, 9)
+    sp5 = q.PixelSampler.sobol(q.from_u32(q.qmc_sobol_matrices(64, sobol_direction_init(64, 0))), 0xC5)
+    gm5 = torch.full((W5 * H5,), 1e-8, dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
-    q.qmc_integrate_pixels(sp, ig3, W, H, dc3)
-    torch.cuda.synchronize()
-    q.qmc_integrate_pixels(sp, ig4, W, H, dc4)
-    torch.cuda.synchronize()
-    q.qmc_integrate_pixels_backward(sp, ig4, W, H, dc4, gm)
-    torch.cuda.synchronize()
+    for launch in (lambda: q.qmc_integrate_pixels(sp, ig3, W, H, dc3),
+                   lambda: q.qmc_integrate_pixels(sp, ig4, W, H, dc4),
+                   lambda: q.qmc_integrate_pixels_backward(sp, ig4, W, H, dc4, gm),
+                   lambda: q.qmc_integrate_pixels_l2_step(sp, ig4, W, H, dc4, target),
+                   lambda: q.qmc_integrate_pixels(sp5, ig5, W5, H5, dc5, 0, 64),
+                   lambda: q.qmc_integrate_pixels_backward(sp5, ig5, W5, H5, dc5, gm5, sample_begin=0,
+                                                           sample_end=64)):
+        launch()
+        torch.cuda.synchronize()
     print("pmc pixel probe done", flush=True)
 
 

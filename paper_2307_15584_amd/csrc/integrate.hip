@@ -157,6 +157,14 @@ struct PixelLds {
     uint32_t B[D];  // current per-round index part
 };
 
+// Per-wave scramble seeds and shifts of the tile's 64 pixels ([dimension][pixel]), formed once
+// per tile so that packed pixels do not hash per sample.
+template <int D>
+struct PackedSeeds {
+    uint32_t seed[D][kWave];
+    uint32_t shift[D][kWave];
+};
+
 // 2^-e for e >= 0 with the hardware exponential (about 1 ulp); results below 2^-126 may flush
 // to zero, which changes a lobe's contribution by less than 1e-38.
 __device__ __forceinline__ float exp2_neg(float e) { return __builtin_amdgcn_exp2f(-e); }
@@ -245,12 +253,14 @@ __device__ __forceinline__ void index_part(uint32_t (&v)[kGen<D>], const Sampler
 // Components j0 + jj < d (jj < kGen<D>) of sample i of pixel p into x (0 beyond d).
 //   base:   per-round index part in LDS (PixelLds::B or SamplerLds::B0); with it, the Sobol'
 //           index part is base[j] ^ T[j][k] for k = i - begin mod 64.  NULL: C_j i directly.
-//   PX:     per-pixel values of a big pixel (NULL: derive them from the hash per lane);
+//   PX:     per-pixel values of a big pixel; else PK: the tile's per-pixel values, pixel q;
+//           both NULL: derive them from the hash per lane;
 //   valid:  false for lanes past the end of a window, which must not read materialised samples.
 template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK>
 __device__ __forceinline__ void sample_point(float (&x)[kGen<D>], const SamplerLds<D>& S, const PixelLds<D>* PX,
                                              const Args& a, uint32_t p, uint32_t i, uint32_t k,
-                                             const uint32_t* base, bool valid, uint32_t j0) {
+                                             const uint32_t* base, bool valid, uint32_t j0,
+                                             const PackedSeeds<D>* PK = nullptr, uint32_t q = 0) {
     constexpr int G = kGen<D>;
     if constexpr (SK == QMC_SAMPLER_POINTS) {
         const uint64_t off = valid ? a.offsets[p] + i : 0;
@@ -276,6 +286,9 @@ __device__ __forceinline__ void sample_point(float (&x)[kGen<D>], const SamplerL
                     if (PX) {
                         sd = PX->seed[j];
                         sm = PX->sm[j];
+                    } else if (PK) {
+                        sd = PK->seed[j][q];
+                        sm = dev::seed_multiplier(sd);
                     } else {
                         sd = dev::pcg_hash(S.kn[j] ^ p);
                         sm = dev::seed_multiplier(sd);
@@ -283,7 +296,7 @@ __device__ __forceinline__ void sample_point(float (&x)[kGen<D>], const SamplerL
                     v = dev::nus_from_mirrored(v, sd, sm);
                 }
                 if constexpr (SHIFT) {
-                    const uint32_t sh = PX ? PX->shift[j] : dev::pcg_hash(S.kc[j] ^ p);
+                    const uint32_t sh = PX ? PX->shift[j] : PK ? PK->shift[j][q] : dev::pcg_hash(S.kc[j] ^ p);
                     v = a.sxor ? (v ^ sh) : (v + sh);
                 }
                 x[jj] = dev::u32_to_unifloat(v);
@@ -314,7 +327,8 @@ template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK, bool DELTA, typen
           typename BigEnd>
 __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S, PixelLds<D>& PX, uint32_t task,
                                           uint32_t n, bool inb, uint32_t off, uint32_t total_small,
-                                          BigBegin&& on_big_begin, Round&& on_round, BigEnd&& on_big_end) {
+                                          BigBegin&& on_big_begin, Round&& on_round, BigEnd&& on_big_end,
+                                          PackedSeeds<D>* PK = nullptr) {
     constexpr int G = kGen<D>;
     constexpr uint32_t RS = kRoundSamples<D>;
     const uint32_t lane = lane_id();
@@ -377,6 +391,14 @@ __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S,
         wave_sync();
     }
 
+    if (PK && total_small) {
+        // every lane hashes its own pixel's values (pixels without packed samples are unused)
+        for (uint32_t j = 0; j < a.d && j < D; ++j) {
+            if constexpr (NUS) PK->seed[j][lane] = dev::pcg_hash(S.kn[j] ^ (p0 + lane));
+            if constexpr (SHIFT) PK->shift[j][lane] = dev::pcg_hash(S.kc[j] ^ (p0 + lane));
+        }
+        wave_sync();
+    }
     for (uint32_t sb = 0; sb < total_small; sb += RS) {
         const uint32_t g = sb + row;
         const uint32_t count = min(total_small - sb, RS);
@@ -388,7 +410,7 @@ __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S,
         const uint32_t k = valid ? g - offq : 0u;
         float x[G];
         sample_point<D, SK, NUS, SHIFT, BACK>(x, S, nullptr, a, pp, a.begin + k, k & (kWave - 1),
-                                              a.aligned ? S.B0 : nullptr, valid, j0);
+                                              a.aligned ? S.B0 : nullptr, valid, j0, PK, q);
         if constexpr (DELTA) {
 #pragma unroll
             for (int jj = 0; jj < G; ++jj)
@@ -481,9 +503,11 @@ __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
     constexpr int D = 8;
     __shared__ SamplerLds<D> S;
     __shared__ PixelLds<D> PXs[kWavesPerBlock];
+    __shared__ PackedSeeds<D> PKs[kWavesPerBlock];
     stage_sampler<D, SK, NUS>(S, a);
     __syncthreads();
     PixelLds<D>& PX = PXs[threadIdx.x >> 6];
+    PackedSeeds<D>* PK = (NUS || SHIFT) ? &PKs[threadIdx.x >> 6] : nullptr;
     const uint32_t lane = lane_id();
     for_each_task(a, [&](uint32_t task) {
         const TileInfo ti = tile_info(a, task);
@@ -519,7 +543,8 @@ __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
             [&](uint32_t q) {
                 const float t = wave_sum(big_acc);
                 if (lane == 0) write_pixel(a, task * kTile + q, t);
-            });
+            },
+            PK);
         if (ti.inb && ti.n < kWave) write_pixel(a, ti.p, small_acc);
     });
 }
