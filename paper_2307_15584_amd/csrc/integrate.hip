@@ -513,6 +513,10 @@ __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
         const TileInfo ti = tile_info(a, task);
         float big_acc = 0.0f, small_acc = 0.0f;
         GenzPixel gbig;
+        // Each lane holds its own pixel's parameters when the tile has packed samples; a packed
+        // sample fetches its pixel's set from the owner lane.
+        GenzPixel own;
+        if (ti.total && ti.inb && ti.ns) own.load(a, ti.p);
         walk_tile<D, SK, NUS, SHIFT, BACK, false>(
             a, S, PX, task, ti.n, ti.inb, ti.off, ti.total,
             [&](uint32_t q) {
@@ -525,7 +529,13 @@ __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
                     f = gbig.eval(x);
                 } else {
                     GenzPixel g;
-                    g.load(a, pp);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        g.u[j] = __shfl(own.u[j], q, kWave);
+                        g.c[j] = __shfl(own.c[j], q, kWave);
+                        g.b[j] = __shfl(own.b[j], q, kWave);
+                    }
+                    g.phi0 = __shfl(own.phi0, q, kWave);
                     f = g.eval(x);
                 }
                 if (lane >= count) f = 0.0f;
