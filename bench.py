@@ -68,6 +68,17 @@ def _cpu_job(args):
     return time.perf_counter() - t0
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(points=1 << 23, chunks=128):
     """The oracle on a bounded sample of the same workload (first `points` indices, 32 dims)."""
     import multiprocessing as mp
@@ -79,10 +90,11 @@ def cpu_baseline(points=1 << 23, chunks=128):
     with ctx.Pool(cores) as pool:
         pool.map(_cpu_job, [(0, 64)] * cores)  # import warm-up, untimed
         t0 = time.perf_counter()
-        pool.map(_cpu_job, jobs)
+        job_s = pool.map(_cpu_job, jobs)
         wall = time.perf_counter() - t0
     ptdims = points * 32
     return {"value": ptdims / wall / 1e9, "unit": "Gpts·dim/s", "cores": cores, "kind": "oracle",
+            "value_1core": ptdims / sum(job_s) / 1e9, "cpu": _cpu_model(),
             "sample": "first %d indices x 32 dims, scramble + rotation, u32 + float32; %.1f s wall on %d "
                       "processes" % (points, wall, cores)}
 
@@ -100,7 +112,8 @@ def _timed(torch, fn, reps, warmup=1):
 
 
 # ALU roofline of the fused pixel kernels.  One lane-op = one 32-bit VALU operation on one lane;
-# the fp32 vector peak (157.3 TFLOP/s, an FMA counted as 2) is 78.6 T lane-ops/s.
+# the peak is 256 CUs x 2.4 GHz x 2 wave64 instructions per CU per cycle = 78.6 T lane-ops/s
+# (FMA-class instructions alone issue at half that rate).
 VALU_PEAK_T = 78.6
 GEN_OPS_PER_DIM = 20      # index part 1, nested scramble 11, rotation 1, conversion 7
 GENZ_EVAL_OPS = 21        # Gaussian 12, phase 4, range reduction 2, exp2 + cos + product 3
