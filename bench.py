@@ -96,7 +96,50 @@ def cpu_baseline(points=1 << 23, chunks=128):
     return {"value": ptdims / wall / 1e9, "unit": "Gpts·dim/s", "cores": cores, "kind": "oracle",
             "value_1core": ptdims / sum(job_s) / 1e9, "cpu": _cpu_model(),
             "sample": "first %d indices x 32 dims, scramble + rotation, u32 + float32; %.1f s wall on %d "
-                      "processes" % (points, wall, cores)}
+                      "processes" % (points, wall, cores),
+            "pixels": cpu_pixel_oracle()}
+
+
+def cpu_pixel_oracle():
+    """The oracle's per-pixel estimator, one core, on crops of the pixel workloads (the crop's
+    pixels keep their full-image indices, seeds and counts)."""
+    import numpy as np
+
+    from oracle import digital, estimator
+    from synth import counts_pow2, counts_uniform, genz_params, lobe_params, sobol_direction_init
+
+    W, H = 1920, 1080
+    m8 = digital.sobol_matrices(8, sobol_direction_init(8, 0))
+    sp = {"kind": "sobol", "s": 8, "table": m8, "seed": 0xC3,
+          "flags": estimator.PIXEL_NUS | estimator.PIXEL_SHIFT}
+
+    def crop(n):
+        return (np.arange(n)[:, None] * W + np.arange(n)[None, :]).ravel()
+
+    out = {}
+    c3 = counts_pow2(W, H, 5)
+    ig3 = {"kind": "genz", "d": 8, "pixel_params": genz_params(W * H, 4)}
+    px = crop(96)
+    t0 = time.perf_counter()
+    estimator.integrate_pixels(sp, ig3, c3, px)
+    dt = time.perf_counter() - t0
+    ns = int(c3[px].astype(np.int64).sum())
+    out["genz"] = {"pixel_samples_per_s": round(ns / dt, 1), "cores": 1, "crop": "96x96 pixels, %d samples" % ns}
+    c4 = counts_uniform(W, H, 64)
+    ig4 = {"kind": "lobes", "d": 8, "num_lobes": 64, "params": lobe_params(64, 8, 6), "pixel_seed": 9}
+    px = crop(48)
+    t0 = time.perf_counter()
+    estimator.integrate_pixels(sp, ig4, c4, px)
+    dt = time.perf_counter() - t0
+    out["lobes_fwd"] = {"pixel_samples_per_s": round(len(px) * 64 / dt, 1), "cores": 1,
+                        "crop": "48x48 pixels x 64 spp"}
+    px = crop(12)
+    t0 = time.perf_counter()
+    estimator.loss_and_gradient(sp, ig4, c4, px, np.zeros(len(px)))
+    dt = time.perf_counter() - t0
+    out["lobes_fwd_bwd"] = {"pixel_samples_per_s": round(len(px) * 64 / dt, 1), "cores": 1,
+                            "crop": "12x12 pixels x 64 spp (estimate, L2 loss and analytic gradient)"}
+    return out
 
 
 def _timed(torch, fn, reps, warmup=1):
@@ -109,6 +152,19 @@ def _timed(torch, fn, reps, warmup=1):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def _event_ms(torch, fn, reps):
+    """Mean GPU ms per call from HIP events around reps back-to-back calls on the current stream."""
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
 
 
 # ALU roofline of the fused pixel kernels.  One lane-op = one 32-bit VALU operation on one lane;
@@ -268,7 +324,7 @@ def pixel_workloads(torch, q, reps, progressive):
                 q.qmc_integrate_progressive(smp, ig5, W5, H5, dc5, 16, 64, sums, means5, ws5, use_graph=graph)
             g_ms = _timed(torch, lambda: run(True), 1)
             e_ms = _timed(torch, lambda: run(False), 1)
-            rec[name] = {"graph_ms": round(g_ms, 3), "eager_ms": round(e_ms, 3),
+            rec[name] = {"graph_ms": round(g_ms, 3), "eager_ms": round(e_ms, 3), "per_pass_ms": round(g_ms / 16, 3),
                          "pixel_samples_per_s": round(n5 / (g_ms * 1e-3), 1),
                          "roofline": alu_roofline(n5, lobe_fwd_ops(d5, L5), g_ms)}
         gm5 = torch.full((P5,), 1e-8, dtype=torch.float32, device="cuda")
@@ -432,7 +488,20 @@ def main():
                      "kernel_ms": round(sobol_ms, 4), "algorithmic_bytes": alg_bytes,
                      "fill_gbs": round(fill_gbs, 1), "frac_of_fill": round(achieved / fill_gbs, 4)},
     }
-    del su, sf, lu, lf
+    # the other generation workloads: lattice at the Sobol' size (steady-state roofline) and the
+    # small unscrambled (0,2)-sequence + 2 dims (launch latency)
+    q.qmc_generate_lattice(gvec, 0, n, shifts, 0, out_u32=su, out_f32=sf)
+    lat_ms = _event_ms(torch, lambda: q.qmc_generate_lattice(gvec, 0, n, shifts, 0, out_u32=su, out_f32=sf), 20)
+    out["lattice_2p24x32"] = {"kernel_ms": round(lat_ms, 4), "gbs": round(alg_bytes / (lat_ms * 1e-3) / 1e9, 1),
+                              "frac": round(alg_bytes / (lat_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    m4 = q.from_u32(q.qmc_sobol_matrices(4, sobol_direction_init(4, 0)))
+    c1u = torch.empty((4, 1 << 16), dtype=torch.int32, device="cuda")
+    c1f = torch.empty((4, 1 << 16), dtype=torch.float32, device="cuda")
+    c1_ms = _event_ms(torch, lambda: q.qmc_generate_sobol(m4, 0, 1 << 16, None, None, 0, out_u32=c1u, out_f32=c1f),
+                      200)
+    out["unscrambled_2p16x4"] = {"us_per_launch": round(c1_ms * 1e3, 2),
+                                 "note": "kernel time from HIP events around 200 back-to-back launches"}
+    del su, sf, lu, lf, c1u, c1f
     torch.cuda.empty_cache()
     if not args.no_pixels:
         out["pixels"] = pixel_workloads(torch, q, max(3, args.steps // 4), args.progressive)

@@ -165,6 +165,13 @@ struct PackedSeeds {
     uint32_t shift[D][kWave];
 };
 
+// a + b as a separate add: keeps the compiler from contracting it with the product that formed
+// b into an FMA.  Plain FP32 adds and multiplies issue at twice the rate of FMAs on this chip.
+__device__ __forceinline__ float add_nc(float a, float b) {
+#pragma clang fp contract(off)
+    return a + b;
+}
+
 // 2^-e for e >= 0 with the hardware exponential (about 1 ulp); results below 2^-126 may flush
 // to zero, which changes a lobe's contribution by less than 1e-38.
 __device__ __forceinline__ float exp2_neg(float e) { return __builtin_amdgcn_exp2f(-e); }
@@ -769,14 +776,14 @@ __device__ __forceinline__ void lobes_bwd_tile(const Args& a, const SamplerLds<D
                             for (int jj = 0; jj < LL::DH; ++jj) {
                                 const float tj = fmaf(y[jj], st[jj], b[jj]);
                                 const float gt = gw * tj;
-                                acc_c[jj] += gt;
+                                acc_c[jj] = add_nc(acc_c[jj], gt);
                                 acc_l[jj] = fmaf(gt, tj, acc_l[jj]);
                             }
                         } else {
 #pragma unroll
                             for (int jj = 0; jj < LL::DH; ++jj) {
                                 const float gt = gw * t[jj];
-                                acc_c[jj] += gt;
+                                acc_c[jj] = add_nc(acc_c[jj], gt);
                                 acc_l[jj] = fmaf(gt, t[jj], acc_l[jj]);
                             }
                         }
@@ -912,7 +919,7 @@ __global__ __launch_bounds__(kBlock) void lobes_step(Args a) {
 #pragma unroll
                             for (int jj = 0; jj < LL::DH; ++jj) {
                                 const float gt = wg * t[jj];
-                                pc[jj] += gt;
+                                pc[jj] = add_nc(pc[jj], gt);
                                 pl[jj] = fmaf(gt, t[jj], pl[jj]);
                             }
                         }
