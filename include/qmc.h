@@ -148,12 +148,25 @@ qmc_status qmc_generate_lattice(qmc_context ctx, qmc_stream stream,
  *
  * Sample i of pixel p, dimension j < d (integers until the last step, Sec. 2.1):
  *   SOBOL:   v = C_j a(i);  v = NUS(v; seed_pj) with QMC_PIXEL_NUS;
- *   LATTICE: v = phi_2(i) g_j mod 1 (phi_2(2^32-1-i) with QMC_LATTICE_BACKWARD);
+ *   LATTICE: v = (phi_2(i) + s_p) g_j mod 1 (phi_2(2^32-1-i) with QMC_LATTICE_BACKWARD), in
+ *            32-bit fixed point; s_p = 0 unless QMC_PIXEL_HILBERT_SHIFT (below); g_j = table[j]
+ *            unless QMC_PIXEL_RANDOM_GENERATOR (below);
  *   then v = v + delta_pj mod 2^32 with QMC_PIXEL_SHIFT (v ^ delta_pj with QMC_SHIFT_XOR),
  *   and x = map_u32_to_unifloat(v).
  *   seed_pj  = H(H(seed + 2j) ^ p),  delta_pj = H(H(seed + 2j + 1) ^ p), where H is the
  *   integer hash "pcg" of Jarzynski and Olano (JCGT 2020):
  *   t = v*747796405 + 2891336453; w = ((t >> ((t >> 28) + 4)) ^ t) * 277803737; H = (w >> 22) ^ w.
+ * Lattice options of Sec. 3:
+ *   QMC_PIXEL_RANDOM_GENERATOR (Alg. 4): pixel p's own generator, g_pj = H(H(H(seed + 2j) ^ p)
+ *     + c) | 1 for instance c = 0 (the table is still read but its values are not used);
+ *   QMC_LATTICE_INSTANCES4 (with the above): four instances superimposed in each pixel, sample
+ *     i being point floor(i / 4) of instance c = i mod 4;
+ *   QMC_PIXEL_HILBERT_SHIFT (Eq. PixelShiftedR1LS): s_p = floor(2^32 phi_3(h(x, y))), h the
+ *     index of pixel (x, y) along the Hilbert curve of the 2^k x 2^k square, 2^k the smallest
+ *     power of two >= max(width, height) (at most 32768), visiting the quadrants of every
+ *     square in the order (0,0), (0,1), (1,1), (1,0) (x = column, y = row) with the
+ *     sub-curves of the two quadrants at y < half transposed (the one at x >= half about the
+ *     other diagonal), so that consecutive indices are edge-adjacent pixels.
  *   POINTS:  x = table[j * points_ld + offsets[p] + i] (samples materialised beforehand by
  *   qmc_generate_pixel_samples: the plain generate-then-integrate path).
  *
@@ -169,8 +182,11 @@ qmc_status qmc_generate_lattice(qmc_context ctx, qmc_stream stream,
 #define QMC_SAMPLER_LATTICE 2u
 #define QMC_SAMPLER_POINTS 3u
 
-#define QMC_PIXEL_NUS 4u   /* sampler flag: per-pixel nested uniform scramble (SOBOL) */
-#define QMC_PIXEL_SHIFT 8u /* sampler flag: per-pixel rotation (addition, or XOR with QMC_SHIFT_XOR) */
+#define QMC_PIXEL_NUS 4u                /* sampler flag: per-pixel nested uniform scramble (SOBOL) */
+#define QMC_PIXEL_SHIFT 8u              /* sampler flag: per-pixel rotation (addition, or XOR with QMC_SHIFT_XOR) */
+#define QMC_PIXEL_RANDOM_GENERATOR 16u  /* LATTICE: per-pixel random generator vector (Alg. 4) */
+#define QMC_PIXEL_HILBERT_SHIFT 32u     /* LATTICE: Hilbert-curve shift of phi_2 (Eq. PixelShiftedR1LS) */
+#define QMC_LATTICE_INSTANCES4 64u      /* LATTICE with QMC_PIXEL_RANDOM_GENERATOR: four instances */
 
 #define QMC_F_GENZ 1u
 #define QMC_F_LOBES 2u
@@ -183,7 +199,9 @@ typedef struct {
     uint64_t points_ld;      /* POINTS: leading dimension of table                                 */
     const uint64_t* offsets; /* POINTS: device [P], slot of sample 0 of pixel p                    */
     uint32_t seed;           /* per-pixel seeds and rotations are derived from this                */
-    uint32_t flags;          /* QMC_PIXEL_NUS | QMC_PIXEL_SHIFT | QMC_SHIFT_XOR | QMC_LATTICE_BACKWARD */
+    uint32_t flags;          /* QMC_PIXEL_NUS | QMC_PIXEL_SHIFT | QMC_SHIFT_XOR | QMC_LATTICE_BACKWARD  */
+                             /* | QMC_PIXEL_RANDOM_GENERATOR | QMC_LATTICE_INSTANCES4                  */
+                             /* | QMC_PIXEL_HILBERT_SHIFT (the last three: LATTICE only)              */
 } qmc_sampler;
 
 typedef struct {

@@ -4,9 +4,12 @@ processing element, here per pixel; no communication until the final reduction).
 Pixel p = y * width + x (row-major) integrates with samples i in [0, N_p), N_p = counts[p].
 Sample i of pixel p, dimension j (all integer until the last step, Sec. 2.1):
   Sobol':  v = C_j a(i);  v = NUS_{seed_pj}(v) if scrambling;  v = shift(v, delta_pj) if shifting
-  lattice: v = (phi_2(i) g_j) mod 1 (or backward);            v = shift(v, delta_pj) if shifting
+  lattice: v = ((phi_2(i) + s_p) g_j) mod 1 (or backward);   v = shift(v, delta_pj) if shifting
   x = map_u32_to_unifloat(v)
-with seed_pj = H(H(seed + 2j) ^ p) and delta_pj = H(H(seed + 2j + 1) ^ p).
+with seed_pj = H(H(seed + 2j) ^ p) and delta_pj = H(H(seed + 2j + 1) ^ p).  The lattice
+options of Sec. 3 (see pixel_lattice): g_j may be replaced by the per-pixel random generator
+g_pj (Alg. 4), optionally with four superimposed instances, and s_p is the pixel's Hilbert
+shift floor(2^32 phi_3(h(x, y))) (Eq. PixelShiftedR1LS), else 0.
 
 A call covers the window of sample indices [begin, min(end, N_p)); the window sum is
 added to `sums` and the mean is sums / N_p.  The estimator I_p = (1/N_p) sum_i f_p(x_pi)
@@ -18,14 +21,17 @@ import math
 
 import numpy as np
 
-from . import digital, lattice, scramble, unifloat
-from .integrands import genz, lobes, lobes_weighted_gradient
+from . import digital, lattice, pixel_lattice, scramble, unifloat
+from .integrands import genz, lobes, lobes_weighted_gradient, lobes_weighted_gradient_abs
 
 # Flag bits shared with the library's public header (values fixed by that interface).
 SHIFT_XOR = 1
 LATTICE_BACKWARD = 2
 PIXEL_NUS = 4
 PIXEL_SHIFT = 8
+PIXEL_RANDOM_GENERATOR = 16
+PIXEL_HILBERT_SHIFT = 32
+LATTICE_INSTANCES4 = 64
 
 
 def window_pairs(counts, pixels, begin, end):
@@ -60,7 +66,7 @@ def pixel_samples_u32(sampler, p, i):
             if flags & PIXEL_NUS:
                 v = scramble.nested_uniform_scramble(v, scramble.pixel_nus_seed(seed, p, j))
         elif kind == "lattice":
-            v = lattice.lattice_point(table[j], i, backward=bool(flags & LATTICE_BACKWARD))
+            v = _pixel_lattice_component(sampler, p, i, j)
         else:
             raise ValueError(kind)
         if flags & PIXEL_SHIFT:
@@ -68,6 +74,28 @@ def pixel_samples_u32(sampler, p, i):
             v = scramble.shift_xor(v, d) if flags & SHIFT_XOR else scramble.shift_add(v, d)
         out[j] = v.astype(np.uint32)
     return out
+
+
+def _pixel_lattice_component(sampler, p, i, j):
+    """Component j of the lattice samples (Sec. 2.4; Alg. 4 and Eq. PixelShiftedR1LS options)."""
+    flags = sampler.get("flags", 0)
+    back = bool(flags & LATTICE_BACKWARD)
+    if not flags & (PIXEL_RANDOM_GENERATOR | PIXEL_HILBERT_SHIFT | LATTICE_INSTANCES4):
+        return lattice.lattice_point(sampler["table"][j], i, backward=back)
+    inst = i & np.uint64(3) if flags & LATTICE_INSTANCES4 else np.zeros_like(i)
+    idx = i >> np.uint64(2) if flags & LATTICE_INSTANCES4 else i
+    v = np.zeros(p.size, dtype=np.uint64)
+    keys = np.stack([p, inst]) if p.size else np.zeros((2, 0), np.uint64)
+    for pp, c in {(int(a), int(b)) for a, b in keys.T}:
+        sel = (p == np.uint64(pp)) & (inst == np.uint64(c))
+        if flags & PIXEL_RANDOM_GENERATOR:
+            g = pixel_lattice.pixel_generator(sampler.get("seed", 0), pp, j, c)
+        else:
+            g = int(sampler["table"][j])
+        sh = (pixel_lattice.pixel_hilbert_shift(pp, sampler["width"], sampler["height"])
+              if flags & PIXEL_HILBERT_SHIFT else 0)
+        v[sel] = pixel_lattice.pixel_lattice_points(g, idx[sel], sh, back)
+    return v
 
 
 def pixel_samples_f32(sampler, p, i):
@@ -148,6 +176,24 @@ def lobes_gradient(sampler, integrand, counts, pixels, grad_means, begin=0, end=
     pos = {int(q): k for k, q in enumerate(pixels)}
     scale = np.array([gm[pos[int(q)]] / n[int(q)] for q in p]) if p.size else np.zeros(0)
     return lobes_weighted_gradient(y, scale, th, L, d)
+
+
+def l2_gradient_term_sizes(sampler, integrand, counts, pixels, target):
+    """Per parameter, sum_p (2/P)(|I_p - T_p| + |I_p|)(1/N_p) sum_i |df(x_pi)/dtheta|: the size of
+    what an FP32 evaluation of the L2 gradient adds up (its dL/dI_p carries an error relative
+    to |I_p|), so eps-scaled it bounds the rounding error of components that cancel.  A test
+    tolerance, not part of the method."""
+    pixels = np.asarray(pixels, dtype=np.int64)
+    L, d = integrand["num_lobes"], integrand["d"]
+    means = integrate_pixels(sampler, integrand, counts, pixels)["mean"]
+    wgt = 2.0 * (np.abs(means - np.asarray(target, dtype=np.float64)) + np.abs(means)) / len(pixels)
+    p, i, starts = window_pairs(counts, pixels, 0, 2**32)
+    x32 = pixel_samples_f32(sampler, p, i)
+    y = x32[:d].astype(np.float64) + pixel_offsets(integrand["pixel_seed"], p, d).astype(np.float64)
+    n = np.asarray(counts, dtype=np.float64)
+    pos = {int(q): k for k, q in enumerate(pixels)}
+    scale = np.array([wgt[pos[int(q)]] / n[int(q)] for q in p]) if p.size else np.zeros(0)
+    return lobes_weighted_gradient_abs(y, scale, np.asarray(integrand["params"], np.float64), L, d)
 
 
 def loss_and_gradient(sampler, integrand, counts, pixels, target, theta=None):

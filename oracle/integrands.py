@@ -86,6 +86,28 @@ def lobes_weighted_gradient(y, scale, theta, num_lobes, dim):
     return np.concatenate([gc.ravel(), gl.ravel(), gw])
 
 
+def lobes_weighted_gradient_abs(y, scale, theta, num_lobes, dim):
+    """sum_n |scale_n| * |d f(y_n) / d theta| per parameter, float64 [L*(2d+1)]: the size of the
+    terms a gradient sum adds up, which bounds its rounding error (a test tolerance, not part of
+    the method)."""
+    c, ell, w = split_theta(theta, num_lobes, dim)
+    L, d = num_lobes, dim
+    gc = np.zeros((L, d))
+    gl = np.zeros((L, d))
+    gw = np.zeros(L)
+    a = np.abs(scale)
+    for k in range(L):
+        sig = np.exp(ell[k])
+        r = (y - c[k][:, None]) / sig[:, None]
+        G = np.exp(-0.5 * np.sum(r * r, axis=0))
+        sG = a * G
+        gw[k] = math.fsum(sG)
+        for j in range(d):
+            gc[k, j] = math.fsum(np.abs(w[k] * sG * r[j] / sig[j]))
+            gl[k, j] = math.fsum(np.abs(w[k] * sG * r[j] * r[j]))
+    return np.concatenate([gc.ravel(), gl.ravel(), gw])
+
+
 def lobes_box_integral(delta, theta, num_lobes, dim):
     """Closed-form integral over x in [0,1)^d of f(x + delta) for one offset vector delta [d]."""
     c, ell, w = split_theta(theta, num_lobes, dim)

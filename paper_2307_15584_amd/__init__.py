@@ -16,9 +16,12 @@ from ._lib import (  # noqa: F401
     QMC_F_GENZ,
     QMC_F_LOBES,
     QMC_LATTICE_BACKWARD,
+    QMC_LATTICE_INSTANCES4,
     QMC_MAX_DEGREE,
     QMC_MAX_DIMS,
+    QMC_PIXEL_HILBERT_SHIFT,
     QMC_PIXEL_NUS,
+    QMC_PIXEL_RANDOM_GENERATOR,
     QMC_PIXEL_SHIFT,
     QMC_SAMPLER_LATTICE,
     QMC_SAMPLER_POINTS,

@@ -22,6 +22,9 @@ QMC_SHIFT_XOR = 1
 QMC_LATTICE_BACKWARD = 2
 QMC_PIXEL_NUS = 4
 QMC_PIXEL_SHIFT = 8
+QMC_PIXEL_RANDOM_GENERATOR = 16
+QMC_PIXEL_HILBERT_SHIFT = 32
+QMC_LATTICE_INSTANCES4 = 64
 QMC_SAMPLER_SOBOL = 1
 QMC_SAMPLER_LATTICE = 2
 QMC_SAMPLER_POINTS = 3

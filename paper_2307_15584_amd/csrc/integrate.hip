@@ -48,6 +48,10 @@ struct Args {
     // sampler
     uint32_t skind, s, seed, sflags;
     uint32_t sxor;  // shift by XOR instead of addition
+    // lattice options of Sec. 3: per-pixel random generator (Alg. 4), four superimposed
+    // instances, Hilbert-curve shift of the radical inverse (Eq. PixelShiftedR1LS)
+    uint32_t lrgen, linst4, lhilbert;
+    uint32_t width, hilbert_order;  // image width; 2^hilbert_order >= max(width, height)
     const uint32_t* table;
     const float* points;
     uint64_t points_ld;
@@ -154,7 +158,9 @@ template <int D>
 struct PixelLds {
     uint32_t seed[D], sm[D], shift[D];
     float delta[D];
-    uint32_t B[D];  // current per-round index part
+    uint32_t B[D];       // current per-round index part
+    uint32_t gen[4][D];  // lattice: per-pixel random generator of each instance
+    uint32_t hshift;     // lattice: the pixel's Hilbert shift of the radical inverse
 };
 
 // Per-wave scramble seeds and shifts of the tile's 64 pixels ([dimension][pixel]), formed once
@@ -163,6 +169,7 @@ template <int D>
 struct PackedSeeds {
     uint32_t seed[D][kWave];
     uint32_t shift[D][kWave];
+    uint32_t hshift[kWave];  // lattice: Hilbert shift of each pixel
 };
 
 // a + b as a separate add: keeps the compiler from contracting it with the product that formed
@@ -257,6 +264,56 @@ __device__ __forceinline__ void index_part(uint32_t (&v)[kGen<D>], const Sampler
     }
 }
 
+// Index of cell (x, y) along the Hilbert curve of the 2^order square: at each scale the quadrant
+// (rx, ry) is visited in the order (0,0), (0,1), (1,1), (1,0), i.e. at position (3 rx) ^ ry, and
+// the coordinates inside it are mapped to the sub-curve's frame (transposed for ry = 0, and for
+// rx = 1 also mirrored), so that consecutive indices are edge-adjacent cells.
+__device__ __forceinline__ uint32_t hilbert_index(uint32_t x, uint32_t y, uint32_t order) {
+    uint32_t d = 0;
+    for (uint32_t h = order; h-- > 0;) {
+        const uint32_t rx = (x >> h) & 1u, ry = (y >> h) & 1u;
+        d += ((3u * rx) ^ ry) << (2u * h);
+        const uint32_t m = (1u << h) - 1u;
+        uint32_t xl = x & m, yl = y & m;
+        if (!ry) {
+            if (rx) {
+                xl = m - xl;
+                yl = m - yl;
+            }
+            const uint32_t t = xl;
+            xl = yl;
+            yl = t;
+        }
+        x = xl;
+        y = yl;
+    }
+    return d;
+}
+
+// floor(2^32 phi_3(n)): the base-3 digits of n mirrored at the point (Sec. 2.2), as the exact
+// quotient (reversed digits) * 2^32 / 3^m.
+__device__ __forceinline__ uint32_t radical_inverse3_u32(uint32_t n) {
+    uint64_t r = 0, pw = 1;
+    while (n) {
+        const uint32_t q = n / 3u;
+        r = r * 3u + (n - 3u * q);
+        pw *= 3u;
+        n = q;
+    }
+    return static_cast<uint32_t>((r << 32) / pw);
+}
+
+// The shift of pixel p = y * width + x in the radical-inverse domain (Eq. PixelShiftedR1LS).
+__device__ __forceinline__ uint32_t pixel_hilbert_shift(const Args& a, uint32_t p) {
+    const uint32_t y = p / a.width, x = p - y * a.width;
+    return radical_inverse3_u32(hilbert_index(x, y, a.hilbert_order));
+}
+
+// Per-pixel random generator component (Alg. 4): H(k + c) | 1 with k = H(H(seed + 2j) ^ p).
+__device__ __forceinline__ uint32_t pixel_generator(uint32_t kn_j, uint32_t p, uint32_t c) {
+    return dev::pcg_hash(dev::pcg_hash(kn_j ^ p) + c) | 1u;
+}
+
 // Components j0 + jj < d (jj < kGen<D>) of sample i of pixel p into x (0 beyond d).
 //   base:   per-round index part in LDS (PixelLds::B or SamplerLds::B0); with it, the Sobol'
 //           index part is base[j] ^ T[j][k] for k = i - begin mod 64.  NULL: C_j i directly.
@@ -277,17 +334,26 @@ __device__ __forceinline__ void sample_point(float (&x)[kGen<D>], const SamplerL
     } else {
         uint32_t ip[G];
         if constexpr (SK == QMC_SAMPLER_SOBOL) index_part<D, NUS>(ip, S, a, i, k, base, j0);
-        const uint32_t bi = (SK == QMC_SAMPLER_LATTICE) ? dev::brev(BACK ? ~i : i) : 0u;
+        // lattice: phi_2 of the index (of the instance's index with four instances), plus the
+        // pixel's Hilbert shift; the generator is shared or the pixel's own (Sec. 2.4, Sec. 3)
+        const uint32_t inst = (SK == QMC_SAMPLER_LATTICE && a.linst4) ? (i & 3u) : 0u;
+        const uint32_t il = (SK == QMC_SAMPLER_LATTICE && a.linst4) ? (i >> 2) : i;
+        uint32_t bi = (SK == QMC_SAMPLER_LATTICE) ? dev::brev(BACK ? ~il : il) : 0u;
+        if (SK == QMC_SAMPLER_LATTICE && a.lhilbert)
+            bi += PX ? PX->hshift : PK ? PK->hshift[q] : pixel_hilbert_shift(a, p);
 #pragma unroll
         for (int jj = 0; jj < G; ++jj) {
             const uint32_t j = j0 + jj;
             x[jj] = 0.0f;
             if (j < a.d) {
                 uint32_t v;
-                if constexpr (SK == QMC_SAMPLER_SOBOL)
+                if constexpr (SK == QMC_SAMPLER_SOBOL) {
                     v = ip[jj];
-                else
-                    v = bi * S.g[j];
+                } else {
+                    uint32_t g = S.g[j];
+                    if (a.lrgen) g = PX ? PX->gen[inst][j] : pixel_generator(S.kn[j], p, inst);
+                    v = bi * g;
+                }
                 if constexpr (NUS) {
                     uint32_t sd, sm;
                     if (PX) {
@@ -357,6 +423,15 @@ __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S,
             if constexpr (SHIFT) PX.shift[lane] = dev::pcg_hash(S.kc[lane] ^ pp);
             if constexpr (DELTA) PX.delta[lane] = pixel_delta(S.kd[lane], pp);
             if constexpr (SK == QMC_SAMPLER_SOBOL) PX.B[lane] = S.B0[lane];
+            if constexpr (SK == QMC_SAMPLER_LATTICE) {
+                if (a.lrgen) {
+                    for (uint32_t c = 0; c < (a.linst4 ? 4u : 1u); ++c)
+                        PX.gen[c][lane] = pixel_generator(S.kn[lane], pp, c);
+                }
+            }
+        }
+        if constexpr (SK == QMC_SAMPLER_LATTICE) {
+            if (a.lhilbert && lane == 0) PX.hshift = pixel_hilbert_shift(a, pp);
         }
         wave_sync();
         on_big_begin(q);
@@ -403,6 +478,9 @@ __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S,
         for (uint32_t j = 0; j < a.d && j < D; ++j) {
             if constexpr (NUS) PK->seed[j][lane] = dev::pcg_hash(S.kn[j] ^ (p0 + lane));
             if constexpr (SHIFT) PK->shift[j][lane] = dev::pcg_hash(S.kc[j] ^ (p0 + lane));
+        }
+        if constexpr (SK == QMC_SAMPLER_LATTICE) {
+            if (a.lhilbert && p0 + lane < a.num_pixels) PK->hshift[lane] = pixel_hilbert_shift(a, p0 + lane);
         }
         wave_sync();
     }
@@ -514,7 +592,7 @@ __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
     stage_sampler<D, SK, NUS>(S, a);
     __syncthreads();
     PixelLds<D>& PX = PXs[threadIdx.x >> 6];
-    PackedSeeds<D>* PK = (NUS || SHIFT) ? &PKs[threadIdx.x >> 6] : nullptr;
+    PackedSeeds<D>* PK = (NUS || SHIFT || SK == QMC_SAMPLER_LATTICE) ? &PKs[threadIdx.x >> 6] : nullptr;
     const uint32_t lane = lane_id();
     for_each_task(a, [&](uint32_t task) {
         const TileInfo ti = tile_info(a, task);
@@ -1112,13 +1190,28 @@ qmc_status validate_sampler(const char* who, const qmc_sampler* sp, uint32_t d) 
         return fail(QMC_ERR_INVALID_ARGUMENT, "%s: unknown sampler kind %u", who, sp->kind);
     if (!sp->table) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: sampler table is NULL", who);
     if (sp->s == 0 || sp->s > QMC_MAX_DIMS) return fail(QMC_ERR_OUT_OF_RANGE, "%s: sampler s out of range", who);
-    const uint32_t allowed = QMC_PIXEL_NUS | QMC_PIXEL_SHIFT | QMC_SHIFT_XOR | QMC_LATTICE_BACKWARD;
+    const uint32_t lattice_only = QMC_PIXEL_RANDOM_GENERATOR | QMC_LATTICE_INSTANCES4 | QMC_PIXEL_HILBERT_SHIFT;
+    const uint32_t allowed = QMC_PIXEL_NUS | QMC_PIXEL_SHIFT | QMC_SHIFT_XOR | QMC_LATTICE_BACKWARD | lattice_only;
     if (sp->flags & ~allowed) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: unknown sampler flags", who);
     if (sp->kind != QMC_SAMPLER_SOBOL && (sp->flags & QMC_PIXEL_NUS))
         return fail(QMC_ERR_INVALID_ARGUMENT, "%s: only the Sobol' sampler has a nested scramble", who);
+    if (sp->kind != QMC_SAMPLER_LATTICE && (sp->flags & lattice_only))
+        return fail(QMC_ERR_INVALID_ARGUMENT, "%s: generator and Hilbert-shift options are for the lattice sampler",
+                    who);
+    if ((sp->flags & QMC_LATTICE_INSTANCES4) && !(sp->flags & QMC_PIXEL_RANDOM_GENERATOR))
+        return fail(QMC_ERR_INVALID_ARGUMENT, "%s: four instances need per-pixel random generators", who);
     if (sp->kind == QMC_SAMPLER_POINTS && !sp->offsets)
         return fail(QMC_ERR_INVALID_ARGUMENT, "%s: POINTS sampler needs offsets", who);
     if (d > sp->s) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: integrand needs d = %u > sampler s = %u", who, d, sp->s);
+    return QMC_OK;
+}
+
+// The Hilbert shift indexes the 2^k x 2^k square covering the image; k <= 15 keeps the curve
+// index and the exact base-3 inversion within 64-bit arithmetic.
+qmc_status validate_hilbert(const char* who, const qmc_sampler* sp, uint32_t W, uint32_t H) {
+    if ((sp->flags & QMC_PIXEL_HILBERT_SHIFT) && std::max(W, H) > 32768u)
+        return fail(QMC_ERR_OUT_OF_RANGE, "%s: the Hilbert shift supports images up to 32768 pixels wide and high",
+                    who);
     return QMC_OK;
 }
 
@@ -1138,6 +1231,7 @@ qmc_status validate(const char* who, qmc_context ctx, const qmc_sampler* sp, con
         return fail(QMC_ERR_INVALID_ARGUMENT, "%s: unknown integrand kind %u", who, ig->kind);
     }
     qmc_status st = validate_sampler(who, sp, ig->d);
+    if (st == QMC_OK) st = validate_hilbert(who, sp, W, H);
     if (st != QMC_OK) return st;
     if (uint64_t(W) * H == 0 || uint64_t(W) * H > 0xFFFFFFFFull - kTile)
         return fail(QMC_ERR_OUT_OF_RANGE, "%s: image size out of range", who);
@@ -1215,8 +1309,21 @@ struct SamplesFam {
     }
 };
 
-Args base_args(const qmc_sampler* sp, uint32_t d, uint32_t P, const uint32_t* counts, uint32_t begin, uint32_t end) {
+uint32_t hilbert_order_of(uint32_t W, uint32_t H) {
+    uint32_t k = 1;
+    while ((uint64_t(1) << k) < std::max(W, H)) ++k;
+    return k;
+}
+
+Args base_args(const qmc_sampler* sp, uint32_t d, uint32_t W, uint32_t H, const uint32_t* counts, uint32_t begin,
+               uint32_t end) {
+    const uint32_t P = W * H;
     Args a{};
+    a.lrgen = (sp->flags & QMC_PIXEL_RANDOM_GENERATOR) ? 1u : 0u;
+    a.linst4 = (sp->flags & QMC_LATTICE_INSTANCES4) ? 1u : 0u;
+    a.lhilbert = (sp->flags & QMC_PIXEL_HILBERT_SHIFT) ? 1u : 0u;
+    a.width = W;
+    a.hilbert_order = hilbert_order_of(W, H);
     a.skind = sp->kind;
     a.s = sp->s;
     a.seed = sp->seed;
@@ -1265,7 +1372,7 @@ qmc_status integrate_common(const char* who, qmc_context ctx, qmc_stream stream,
     DeviceGuard guard(ctx->device);
     if (guard.status != QMC_OK) return guard.status;
     hipStream_t hs = as_stream(stream);
-    Args a = base_args(sp, ig->d, P, counts, begin, end);
+    Args a = base_args(sp, ig->d, W, H, counts, begin, end);
     a.fkind = ig->kind;
     a.L = ig->num_lobes;
     a.pixel_seed = ig->pixel_seed;
@@ -1387,6 +1494,7 @@ extern "C" qmc_status qmc_generate_pixel_samples(qmc_context ctx, qmc_stream str
     if (sampler->kind == QMC_SAMPLER_POINTS) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: sampler must generate", who);
     if (d == 0 || d > QMC_MAX_DIMS) return fail(QMC_ERR_OUT_OF_RANGE, "%s: d out of range", who);
     qmc_status st = validate_sampler(who, sampler, d);
+    if (st == QMC_OK) st = validate_hilbert(who, sampler, width, height);
     if (st != QMC_OK) return st;
     if (uint64_t(width) * height == 0 || uint64_t(width) * height > 0xFFFFFFFFull - kTile)
         return fail(QMC_ERR_OUT_OF_RANGE, "%s: image size out of range", who);
@@ -1395,7 +1503,7 @@ extern "C" qmc_status qmc_generate_pixel_samples(qmc_context ctx, qmc_stream str
     if (guard.status != QMC_OK) return guard.status;
     hipStream_t hs = as_stream(stream);
     const uint32_t P = width * height;
-    Args a = base_args(sampler, d, P, counts, 0u, 0xFFFFFFFFu);
+    Args a = base_args(sampler, d, width, height, counts, 0u, 0xFFFFFFFFu);
     a.offsets = offsets;
     a.out = out;
     a.out_ld = ld;

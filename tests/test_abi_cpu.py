@@ -77,3 +77,18 @@ def test_generation_rejects_null_context(lib):
     assert b"context" in lib.qmc_last_error()
     st = lib.qmc_generate_lattice(None, None, ctypes.c_void_p(16), 4, 0, 16, None, 0, ctypes.c_void_p(4096), None, 16)
     assert st == 1
+
+
+def test_header_constants_match_the_binding():
+    """Every #define QMC_* integer in the header has the same value in the Python binding."""
+    from paper_2307_15584_amd import _lib
+
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    defines = dict(re.findall(r"#define\s+(QMC_[A-Z0-9_]+)\s+(\d+)u?\b", text))
+    assert "QMC_PIXEL_HILBERT_SHIFT" in defines and "QMC_LATTICE_INSTANCES4" in defines
+    for name, value in defines.items():
+        if hasattr(_lib, name):
+            assert getattr(_lib, name) == int(value), name
+    for name in ("QMC_PIXEL_NUS", "QMC_PIXEL_SHIFT", "QMC_PIXEL_RANDOM_GENERATOR", "QMC_PIXEL_HILBERT_SHIFT",
+                 "QMC_LATTICE_INSTANCES4", "QMC_SHIFT_XOR", "QMC_LATTICE_BACKWARD"):
+        assert hasattr(_lib, name), name

@@ -150,3 +150,30 @@ def test_unscrambled_coordinate_mean_is_exact():
         x = estimator.pixel_samples_f32(sampler, np.zeros(n, np.int64), np.arange(n))
         for j in range(8):
             assert math.fsum(x[j].astype(np.float64)) / n == (n - 1) / (2.0 * n)
+
+
+def test_gradient_term_sizes_bound_the_gradient():
+    """The term sizes used to bound rounding error dominate the gradient they describe, and
+    equal it where every term has the same sign (a target far below every estimate makes all
+    dL/dI_p positive, and the weight derivatives G are positive)."""
+    from oracle import estimator
+    from synth import counts_uniform, lobe_params
+
+    W, H, L, d = 6, 3, 4, 3
+    counts = counts_uniform(W, H, 16)
+    theta = lobe_params(L, d, 6)
+    sp = {"kind": "sobol", "s": d, "table": digital.sobol_matrices(d, sobol_direction_init(d, 0)), "seed": 3,
+          "flags": estimator.PIXEL_NUS | estimator.PIXEL_SHIFT}
+    ig = {"kind": "lobes", "d": d, "num_lobes": L, "params": theta, "pixel_seed": 9}
+    rng = np.random.default_rng(1)
+    target = rng.uniform(0, 1, W * H)
+    _, g, means = estimator.loss_and_gradient(sp, ig, counts, range(W * H), target)
+    sizes = estimator.l2_gradient_term_sizes(sp, ig, counts, range(W * H), target)
+    assert np.all(sizes >= np.abs(g) * (1 - 1e-12))
+    low = np.full(W * H, -100.0)
+    _, g2, m2 = estimator.loss_and_gradient(sp, ig, counts, range(W * H), low)
+    s2 = estimator.l2_gradient_term_sizes(sp, ig, counts, range(W * H), low)
+    # weights: all terms positive; the sizes add |I_p| to |I_p - T_p|
+    ratio = (np.abs(m2 - low) + np.abs(m2)) / np.abs(m2 - low)
+    gw, sw = g2[2 * L * d:], s2[2 * L * d:]
+    assert np.all(sw <= gw * ratio.max() * (1 + 1e-12)) and np.all(sw >= gw * ratio.min() * (1 - 1e-12))
