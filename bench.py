@@ -238,6 +238,17 @@ def pixel_workloads(torch, q, reps, progressive):
         "plain_pixel_samples_per_s": round(n3 / (plain_ms3 * 1e-3), 1),
         "speedup_vs_plain": round(plain_ms3 / fused3, 3),
         "roofline": alu_roofline(n3, 8 * GEN_OPS_PER_DIM + GENZ_EVAL_OPS, fused3)}
+    # the same workload under the lattice samplers of Sec. 3 (shared generator with the pixel's
+    # Hilbert shift; per-pixel random generators, four instances)
+    gl = q.from_u32(lattice_vector(8, 30, 3))
+    lat = {}
+    for name, flags in (("pixel_shifted_lattice", q.QMC_PIXEL_HILBERT_SHIFT),
+                        ("random_lattice_4_instances", q.QMC_PIXEL_RANDOM_GENERATOR | q.QMC_LATTICE_INSTANCES4
+                         | q.QMC_LATTICE_BACKWARD)):
+        smp = q.PixelSampler.lattice(gl, 0xC3, flags)
+        ms = _timed(torch, lambda: q.qmc_integrate_pixels(smp, ig3, W, H, dc3, means=means, workspace=ws3), reps)
+        lat[name] = {"fused_ms": round(ms, 4), "fused_pixel_samples_per_s": round(n3 / (ms * 1e-3), 1)}
+    out["genz_1920x1080_uneven"]["lattice_samplers"] = lat
     del pts3
 
     # Gaussian lobes, forward + L2 gradient + adjoint

@@ -16,6 +16,9 @@ Modules:
               matrices and points (Sec. 2.2, 2.3, Eq. ts)
   scramble    nested uniform scramble, shifts, the per-pixel hash (Sec. 2.1, 2.3, 2.5.2)
   lattice     rank-1 lattice sequence points (Sec. 2.4, Eq. R1LS, Alg. 4)
+  pixel_lattice  per-pixel lattices of Sec. 3: random generator per pixel (Alg. 4),
+              radical inverse in base b, Hilbert index, pixel-shifted lattice
+              (Eq. PixelShiftedR1LS)
   integrands  Genz and Gaussian-lobe integrands and their parameter gradients
   estimator   per-pixel QMC integro-approximation, loss, analytic and
               finite-difference gradients (Sec. 2.5)
@@ -25,5 +28,7 @@ scrambling without fixing one); its arithmetic has no external value to pin agai
 so its *values* are "parity unpinned" and only its defining properties are pinned
 (nestedness, bijectivity, net preservation).  The per-pixel hash and the integrands
 are likewise builder-defined workloads, pinned by their published definition
-(hash) and by closed-form integrals and finite differences (integrands).
+(hash) and by closed-form integrals and finite differences (integrands).  The per-pixel
+random lattice generator (a hash the paper leaves open) is "parity unpinned" in the
+same way: only its oddness and distinctness are pinned.
 """
