@@ -19,6 +19,8 @@ Modules:
   pixel_lattice  per-pixel lattices of Sec. 3: random generator per pixel (Alg. 4),
               radical inverse in base b, Hilbert index, pixel-shifted lattice
               (Eq. PixelShiftedR1LS)
+  halton      radical inversion in prime bases with identity, Faure or linear digit
+              permutations, and the Halton sequence (Sec. 2.2)
   integrands  Genz and Gaussian-lobe integrands and their parameter gradients
   estimator   per-pixel QMC integro-approximation, loss, analytic and
               finite-difference gradients (Sec. 2.5)
