@@ -505,6 +505,12 @@ def main():
     lat_ms = _event_ms(torch, lambda: q.qmc_generate_lattice(gvec, 0, n, shifts, 0, out_u32=su, out_f32=sf), 20)
     out["lattice_2p24x32"] = {"kernel_ms": round(lat_ms, 4), "gbs": round(alg_bytes / (lat_ms * 1e-3) / 1e9, 1),
                               "frac": round(alg_bytes / (lat_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    hal = {}
+    for name, mode in (("identity", q.QMC_HALTON_IDENTITY), ("faure", q.QMC_HALTON_FAURE)):
+        h_ms = _event_ms(torch, lambda: q.qmc_generate_halton(s, 0, n, mode, None, out_u32=su, out_f32=sf), 10)
+        hal[name] = {"kernel_ms": round(h_ms, 4), "gpts_dim_per_s": round(s * n / (h_ms * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(alg_bytes / (h_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    out["halton_2p24x32"] = hal
     m4 = q.from_u32(q.qmc_sobol_matrices(4, sobol_direction_init(4, 0)))
     c1u = torch.empty((4, 1 << 16), dtype=torch.int32, device="cuda")
     c1f = torch.empty((4, 1 << 16), dtype=torch.float32, device="cuda")

@@ -91,6 +91,28 @@ qmc_status qmc_sobol_matrices(uint32_t s, const uint32_t* direction_init, uint32
 
 /* ------------------------------------------------------------- generation ---- */
 
+/* Halton sequence (Sec. 2.2): component j of point i is
+ *   v = floor(2^32 phi_{b_j,sigma}(i mod b_j^M)),   x = map_u32_to_unifloat(v),
+ * with b_j the j-th prime (2, 3, 5, ..., 311 for j < 64), b_j^M the largest power of b_j that
+ * fits in 32 bits (the listing's max_powers), and phi_{b,sigma}(k) = sum_t sigma(a_t(k)) b^(-t-1)
+ * for the base-b digits a_t(k).  The digit permutation sigma is chosen by `mode`:
+ *   QMC_HALTON_IDENTITY  sigma(a) = a;
+ *   QMC_HALTON_FAURE     Faure's permutations (Sec. 2.2): sigma_2 = (0,1); even b: 2 sigma_{b/2}
+ *                        followed by 2 sigma_{b/2} + 1; odd b: sigma_{b-1} with values
+ *                        >= (b-1)/2 raised by one and (b-1)/2 inserted in the middle;
+ *   QMC_HALTON_LINEAR    sigma(a) = (factors[j] * a) mod b_j (linear digit scrambling; the
+ *                        paper's multiplier table is not printed, so the caller supplies it;
+ *                        a factor that is 0 mod b_j maps every digit to 0; not checked).
+ * Output, layout, first/n/ld rules, alignment fast path and errors as for qmc_generate_sobol.
+ *   s:        1..QMC_MAX_DIMS.
+ *   factors:  device u32 [s], required for QMC_HALTON_LINEAR, else ignored (may be NULL). */
+#define QMC_HALTON_IDENTITY 0u
+#define QMC_HALTON_FAURE 1u
+#define QMC_HALTON_LINEAR 2u
+qmc_status qmc_generate_halton(qmc_context ctx, qmc_stream stream, uint32_t s, uint64_t first, uint64_t n,
+                               uint32_t mode, const uint32_t* factors, uint32_t* out_u32, float* out_f32,
+                               uint64_t ld);
+
 /* map_u32_to_unifloat (Sec. 2.1, Alg. 1) over an array: out[k] = the largest binary32 not
  * above in[k] * 2^-32, so every result lies in [0, 1).  in, out: device, n elements each
  * (may alias exactly).  Errors: INVALID_ARGUMENT (NULL with n > 0). */

@@ -15,6 +15,9 @@ import numpy as np
 from ._lib import (  # noqa: F401
     QMC_F_GENZ,
     QMC_F_LOBES,
+    QMC_HALTON_FAURE,
+    QMC_HALTON_IDENTITY,
+    QMC_HALTON_LINEAR,
     QMC_LATTICE_BACKWARD,
     QMC_LATTICE_INSTANCES4,
     QMC_MAX_DEGREE,
@@ -184,6 +187,22 @@ def qmc_generate_lattice(generator, first, n, shifts=None, flags=0, out_u32=None
     st = load().qmc_generate_lattice(
         context(generator.device), _stream(), _dev_ptr(generator, "generator", _u32_types()), s, first, n,
         _dev_ptr(shifts, "shifts", _u32_types()), flags,
+        _dev_ptr(out_u32, "out_u32", _u32_types()), _dev_ptr(out_f32, "out_f32", (torch.float32,)), ld)
+    check(st)
+    return out_u32, out_f32
+
+
+def qmc_generate_halton(s, first, n, mode=0, factors=None, out_u32=None, out_f32=None, ld=None, want_u32=True,
+                        want_f32=True, device="cuda"):
+    """Points i in [first, first+n) of the Halton sequence in s dimensions (bases: the first s
+    primes), with QMC_HALTON_IDENTITY / _FAURE / _LINEAR digit permutations; factors: device
+    u32 [s] for _LINEAR.  Returns (u32 int32 tensor [s][ld] or None, float32 tensor or None)."""
+    torch = _torch()
+    _check_len(factors, s, "factors")
+    dev = factors.device if factors is not None else torch.device(device)
+    ld, out_u32, out_f32 = _outputs(s, n, ld, out_u32, out_f32, want_u32, want_f32, dev)
+    st = load().qmc_generate_halton(
+        context(dev), _stream(), s, first, n, mode, _dev_ptr(factors, "factors", _u32_types()),
         _dev_ptr(out_u32, "out_u32", _u32_types()), _dev_ptr(out_f32, "out_f32", (torch.float32,)), ld)
     check(st)
     return out_u32, out_f32

@@ -25,6 +25,9 @@ QMC_PIXEL_SHIFT = 8
 QMC_PIXEL_RANDOM_GENERATOR = 16
 QMC_PIXEL_HILBERT_SHIFT = 32
 QMC_LATTICE_INSTANCES4 = 64
+QMC_HALTON_IDENTITY = 0
+QMC_HALTON_FAURE = 1
+QMC_HALTON_LINEAR = 2
 QMC_SAMPLER_SOBOL = 1
 QMC_SAMPLER_LATTICE = 2
 QMC_SAMPLER_POINTS = 3
@@ -67,6 +70,7 @@ SIGNATURES = {
     "qmc_map_u32_to_unifloat": (_st, [_vp, _vp, _vp, _vp, _u64]),
     "qmc_generate_sobol": (_st, [_vp, _vp, _vp, _u32, _u64, _u64, _vp, _vp, _u32, _vp, _vp, _u64]),
     "qmc_generate_lattice": (_st, [_vp, _vp, _vp, _u32, _u64, _u64, _vp, _u32, _vp, _vp, _u64]),
+    "qmc_generate_halton": (_st, [_vp, _vp, _u32, _u64, _u64, _u32, _vp, _vp, _vp, _u64]),
     "qmc_workspace_size": (_st, [_vp, _vp, _vp, _u32, _u32, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "qmc_integrate_pixels": (_st, [_vp, _vp, _vp, _vp, _u32, _u32, _vp, _u32, _u32, _vp, _vp, _vp,
                                    ctypes.c_size_t]),

@@ -263,6 +263,187 @@ __global__ __launch_bounds__(kBlock) void lattice_general(const uint32_t* __rest
     }
 }
 
+
+// ------------------------------------------------------------------ Halton ----
+//
+// Radical inversion in prime bases (Sec. 2.2): component j of point i is
+// floor(2^32 phi_{b,sigma}(i mod b^M)) with b the j-th prime and b^M the largest power of b in
+// 32 bits.  With all M digits formed (leading zeros included; sigma(0) = 0 for every
+// permutation used), phi = R / b^M for the mirrored digit integer R, so one exact division
+// by a per-dimension constant ends the loop.  Digits come from a multiply by floor(2^32 / b)
+// and one correction step; base 2 is the bit reversal of the reduced index.
+
+__constant__ uint32_t kPrimes[QMC_MAX_DIMS] = {
+    2,   3,   5,   7,   11,  13,  17,  19,  23,  29,  31,  37,  41,  43,  47,  53,  59,  61,  67,  71,  73,  79,
+    83,  89,  97,  101, 103, 107, 109, 113, 127, 131, 137, 139, 149, 151, 157, 163, 167, 173, 179, 181, 191, 193,
+    197, 199, 211, 223, 227, 229, 233, 239, 241, 251, 257, 263, 269, 271, 277, 281, 283, 293, 307, 311};
+
+constexpr uint32_t kMaxBase = 311;
+
+struct HaltonBase {
+    uint32_t b, digits, maxpow, rcp;
+    uint32_t zero2;  // base 2 with an even linear factor: sigma = (0, 0), every value is 0
+    double inv_maxpow, scale;
+};
+
+__device__ __forceinline__ HaltonBase halton_base(uint32_t b) {
+    HaltonBase h;
+    h.b = b;
+    uint64_t q = b;
+    uint32_t m = 1;
+    while (q * b <= 0xFFFFFFFFull) {
+        q *= b;
+        ++m;
+    }
+    h.digits = m;
+    h.maxpow = static_cast<uint32_t>(q);
+    h.rcp = static_cast<uint32_t>((uint64_t(1) << 32) / b);
+    h.inv_maxpow = 1.0 / static_cast<double>(q);
+    h.scale = 4294967296.0 / static_cast<double>(q);
+    h.zero2 = 0;
+    return h;
+}
+
+// Size of the table after `steps` reductions of Faure's recursion from b (b -> b/2 if even,
+// b -> b-1 if odd).
+__device__ __forceinline__ uint32_t faure_chain(uint32_t b, uint32_t steps) {
+    for (uint32_t k = 0; k < steps; ++k) b = (b & 1u) ? b - 1u : b >> 1;
+    return b;
+}
+
+// Digit permutation of base b into sig (one wavefront).  MODE 1: Faure's permutation, built
+// from sigma_2 = (0, 1) up the chain of sizes (even y: 2 sigma_{y/2} then 2 sigma_{y/2} + 1;
+// odd y: sigma_{y-1} with values >= (y-1)/2 raised and (y-1)/2 in the middle).  MODE 2:
+// sigma(a) = f a mod b.  Returns the buffer that holds it.
+template <uint32_t MODE>
+__device__ uint32_t* build_permutation(uint32_t b, uint32_t f, uint32_t (&buf)[2][kMaxBase + 1]) {
+    const uint32_t lane = threadIdx.x;
+    if constexpr (MODE == 2) {
+        for (uint32_t a = lane; a < b; a += kWave) buf[0][a] = static_cast<uint32_t>((uint64_t(f) * a) % b);
+        __syncthreads();
+        return buf[0];
+    } else {
+        uint32_t len = 0;
+        while (faure_chain(b, len) > 2) ++len;
+        if (lane < 2) buf[0][lane] = lane;
+        uint32_t cur = 0;
+        __syncthreads();
+        for (uint32_t k = len; k-- > 0;) {
+            const uint32_t y = faure_chain(b, k);
+            for (uint32_t a = lane; a < y; a += kWave) {
+                uint32_t v;
+                if (!(y & 1u)) {
+                    const uint32_t h = y >> 1;
+                    v = a < h ? 2u * buf[cur][a] : 2u * buf[cur][a - h] + 1u;
+                } else {
+                    const uint32_t c = (y - 1u) >> 1;
+                    if (a == c) {
+                        v = c;
+                    } else {
+                        const uint32_t t = buf[cur][a < c ? a : a - 1u];
+                        v = t >= c ? t + 1u : t;
+                    }
+                }
+                buf[cur ^ 1u][a] = v;
+            }
+            __syncthreads();
+            cur ^= 1u;
+        }
+        return buf[cur];
+    }
+}
+
+// floor(2^32 phi_{b,sigma}(i mod b^M)) for b >= 3.
+template <uint32_t MODE>
+__device__ __forceinline__ uint32_t halton_component(uint32_t i, const HaltonBase& h, const uint32_t* sig) {
+    uint32_t q = static_cast<uint32_t>(static_cast<double>(i) * h.inv_maxpow);
+    uint64_t t = uint64_t(q) * h.maxpow;
+    if (t > i) {  // the estimate can be one too high or too low
+        --q;
+        t -= h.maxpow;
+    } else if (i - t >= h.maxpow) {
+        ++q;
+        t += h.maxpow;
+    }
+    uint32_t x = static_cast<uint32_t>(i - t);
+    uint32_t r = 0;
+    for (uint32_t k = 0; k < h.digits; ++k) {
+        uint32_t qq = __umulhi(x, h.rcp);
+        uint32_t d = x - qq * h.b;
+        if (d >= h.b) {
+            ++qq;
+            d -= h.b;
+        }
+        r = r * h.b + (MODE == 0 ? d : sig[d]);
+        x = qq;
+    }
+    uint32_t v = static_cast<uint32_t>(static_cast<double>(r) * h.scale);
+    const uint64_t num = uint64_t(r) << 32;
+    const uint64_t den = uint64_t(v) * h.maxpow;
+    if (den > num)
+        --v;
+    else if (num - den >= h.maxpow)
+        ++v;
+    return v;
+}
+
+template <uint32_t MODE>
+__device__ __forceinline__ uint32_t halton_value(uint32_t i, const HaltonBase& h, const uint32_t* sig) {
+    if (h.b == 2) return h.zero2 ? 0u : dev::brev(i & 0x7FFFFFFFu);
+    return halton_component<MODE>(i, h, sig);
+}
+
+// Block (x, j): dimension j, chunks [x * cpw, min((x + 1) * cpw, nchunks)) of 256 indices, four
+// consecutive indices per lane (first % 4 == 0, ld % 4 == 0, 16-byte aligned outputs).
+template <uint32_t MODE, bool WU, bool WF, bool NT>
+__global__ __launch_bounds__(kWave) void halton_fast(uint32_t first, uint32_t n, const uint32_t* __restrict__ factors,
+                                                     uint32_t* __restrict__ ou, float* __restrict__ of, uint64_t ld,
+                                                     uint32_t cpw, uint32_t nchunks) {
+    dev::set_fp32_round_toward_zero();
+    __shared__ uint32_t buf[2][kMaxBase + 1];
+    const uint32_t j = blockIdx.y;
+    HaltonBase h = halton_base(kPrimes[j]);
+    const uint32_t f = MODE == 2 ? factors[j] : 1u;
+    if (MODE == 2 && h.b == 2) h.zero2 = (f & 1u) ? 0u : 1u;
+    const uint32_t* sig = nullptr;
+    if constexpr (MODE != 0) sig = build_permutation<MODE>(h.b, f, buf);
+    const uint32_t lane = threadIdx.x;
+    const uint32_t cb = blockIdx.x * cpw;
+    const uint32_t ce = min(cb + cpw, nchunks);
+    const uint64_t base = uint64_t(j) * ld;
+    for (uint32_t c = cb; c < ce; ++c) {
+        const uint32_t o = c * kChunk + 4u * lane;
+        const uint32_t i = first + o;
+        const uint32_t v0 = halton_value<MODE>(i, h, sig), v1 = halton_value<MODE>(i + 1u, h, sig);
+        const uint32_t v2 = halton_value<MODE>(i + 2u, h, sig), v3 = halton_value<MODE>(i + 3u, h, sig);
+        if (o + 4u <= n)
+            emit4<false, false, WU, WF, NT>(ou, of, base + o, 4u, v0, v1, v2, v3, 0u);
+        else if (o < n)
+            emit4<false, false, WU, WF, NT>(ou, of, base + o, n - o, v0, v1, v2, v3, 0u);
+    }
+}
+
+// Any alignment: block (x, j) covers indices x * 64 + lane + k * 64 * gridDim.x of dimension j.
+template <uint32_t MODE, bool WU, bool WF>
+__global__ __launch_bounds__(kWave) void halton_general(uint32_t first, uint32_t n,
+                                                        const uint32_t* __restrict__ factors,
+                                                        uint32_t* __restrict__ ou, float* __restrict__ of,
+                                                        uint64_t ld) {
+    dev::set_fp32_round_toward_zero();
+    __shared__ uint32_t buf[2][kMaxBase + 1];
+    const uint32_t j = blockIdx.y;
+    HaltonBase h = halton_base(kPrimes[j]);
+    const uint32_t f = MODE == 2 ? factors[j] : 1u;
+    if (MODE == 2 && h.b == 2) h.zero2 = (f & 1u) ? 0u : 1u;
+    const uint32_t* sig = nullptr;
+    if constexpr (MODE != 0) sig = build_permutation<MODE>(h.b, f, buf);
+    for (uint32_t o = blockIdx.x * kWave + threadIdx.x; o < n; o += gridDim.x * kWave) {
+        const uint32_t v = halton_value<MODE>(first + o, h, sig);
+        if constexpr (WU) ou[uint64_t(j) * ld + o] = v;
+        if constexpr (WF) of[uint64_t(j) * ld + o] = dev::u32_to_unifloat_rtz(v);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void unifloat_vec(const u32x4* __restrict__ in, f32x4* __restrict__ out,
                                                        uint64_t nvec) {
     dev::set_fp32_round_toward_zero();
@@ -444,6 +625,57 @@ extern "C" qmc_status qmc_generate_lattice(qmc_context ctx, qmc_stream stream, c
             });
         });
     });
+    return check_launch(who);
+}
+
+extern "C" qmc_status qmc_generate_halton(qmc_context ctx, qmc_stream stream, uint32_t s, uint64_t first, uint64_t n,
+                                          uint32_t mode, const uint32_t* factors, uint32_t* out_u32, float* out_f32,
+                                          uint64_t ld) {
+    const char* who = "qmc_generate_halton";
+    if (mode > QMC_HALTON_LINEAR) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: unknown permutation mode %u", who, mode);
+    if (mode == QMC_HALTON_LINEAR && !factors && n)
+        return fail(QMC_ERR_INVALID_ARGUMENT, "%s: linear scrambling needs factors", who);
+    // validate_generation wants a table; the factors (or any non-NULL marker) stand in for it
+    static const uint32_t marker = 0;
+    qmc_status st = validate_generation(who, ctx, factors ? static_cast<const void*>(factors) : &marker,
+                                        factors ? 4 : 0, s, first, n, 0, 0, nullptr, nullptr, out_u32, out_f32, ld);
+    if (st != QMC_OK || n == 0) return st;
+    if (n > (uint64_t(1) << 31)) {
+        const uint64_t hh = uint64_t(1) << 31;
+        st = qmc_generate_halton(ctx, stream, s, first, hh, mode, factors, out_u32, out_f32, ld);
+        if (st != QMC_OK) return st;
+        return qmc_generate_halton(ctx, stream, s, first + hh, n - hh, mode, factors,
+                                   out_u32 ? out_u32 + hh : nullptr, out_f32 ? out_f32 + hh : nullptr, ld);
+    }
+    DeviceGuard guard(ctx->device);
+    if (guard.status != QMC_OK) return guard.status;
+    hipStream_t hs = as_stream(stream);
+    const bool fast = (first % 4 == 0) && (ld % 4 == 0) && aligned16(out_u32) && aligned16(out_f32);
+    const uint32_t first32 = static_cast<uint32_t>(first);
+    const uint32_t nn = static_cast<uint32_t>(n);
+    clear_launch_error();
+    auto launch = [&](auto MODE) {
+        with_outputs(out_u32 != nullptr, out_f32 != nullptr, [&](auto WU, auto WF) {
+            if (fast) {
+                const uint32_t nchunks = static_cast<uint32_t>((n + kChunk - 1) / kChunk);
+                const uint32_t cpw = 4;  // per-wavefront permutation set-up amortised over 1024 indices
+                hipLaunchKernelGGL((halton_fast<decltype(MODE)::value, WU.value, WF.value, false>),
+                                   dim3((nchunks + cpw - 1) / cpw, s), dim3(kWave), 0, hs, first32, nn, factors,
+                                   out_u32, out_f32, ld, cpw, nchunks);
+            } else {
+                const uint64_t want = (n + kWave - 1) / kWave;
+                const uint32_t gx = static_cast<uint32_t>(std::min<uint64_t>(want, uint64_t(ctx->num_cus) * 16));
+                hipLaunchKernelGGL((halton_general<decltype(MODE)::value, WU.value, WF.value>), dim3(gx, s),
+                                   dim3(kWave), 0, hs, first32, nn, factors, out_u32, out_f32, ld);
+            }
+        });
+    };
+    if (mode == QMC_HALTON_FAURE)
+        launch(std::integral_constant<uint32_t, 1>{});
+    else if (mode == QMC_HALTON_LINEAR)
+        launch(std::integral_constant<uint32_t, 2>{});
+    else
+        launch(std::integral_constant<uint32_t, 0>{});
     return check_launch(who);
 }
 
