@@ -511,6 +511,13 @@ def main():
         hal[name] = {"kernel_ms": round(h_ms, 4), "gpts_dim_per_s": round(s * n / (h_ms * 1e-3) / 1e9, 1),
                      "hbm_frac": round(alg_bytes / (h_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     out["halton_2p24x32"] = hal
+    pm_u = su.view(n, s)
+    pm_f = sf.view(n, s)
+    pm_ms = _event_ms(torch, lambda: q.qmc_generate_sobol(mats, 0, n, seeds, shifts, q.QMC_POINT_MAJOR, out_u32=pm_u,
+                                                          out_f32=pm_f, ld=s), 5)
+    out["sobol_point_major_2p24x32"] = {"kernel_ms": round(pm_ms, 4),
+                                        "gpts_dim_per_s": round(s * n / (pm_ms * 1e-3) / 1e9, 1),
+                                        "hbm_frac": round(alg_bytes / (pm_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     m4 = q.from_u32(q.qmc_sobol_matrices(4, sobol_direction_init(4, 0)))
     c1u = torch.empty((4, 1 << 16), dtype=torch.int32, device="cuda")
     c1f = torch.empty((4, 1 << 16), dtype=torch.float32, device="cuda")

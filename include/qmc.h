@@ -54,6 +54,7 @@ typedef void* qmc_stream;
 /* flags */
 #define QMC_SHIFT_XOR 1u        /* shift by XOR (digital shift, Sec. 2.3) instead of addition mod 2^32 */
 #define QMC_LATTICE_BACKWARD 2u /* lattice: enumerate phi_2(2^32-1-i) so the origin comes last (Alg. 4) */
+#define QMC_POINT_MAJOR 128u    /* generation: out[(i-first)*ld + j] (ld >= s) instead of out[j*ld + (i-first)] */
 
 /* ---------------------------------------------------------------- context ---- */
 
@@ -103,7 +104,8 @@ qmc_status qmc_sobol_matrices(uint32_t s, const uint32_t* direction_init, uint32
  *   QMC_HALTON_LINEAR    sigma(a) = (factors[j] * a) mod b_j (linear digit scrambling; the
  *                        paper's multiplier table is not printed, so the caller supplies it;
  *                        a factor that is 0 mod b_j maps every digit to 0; not checked).
- * Output, layout, first/n/ld rules, alignment fast path and errors as for qmc_generate_sobol.
+ * Output (dimension-major), first/n/ld rules, alignment fast path and errors as for
+ * qmc_generate_sobol without flags.
  *   s:        1..QMC_MAX_DIMS.
  *   factors:  device u32 [s], required for QMC_HALTON_LINEAR, else ignored (may be NULL). */
 #define QMC_HALTON_IDENTITY 0u
@@ -135,7 +137,8 @@ qmc_status qmc_map_u32_to_unifloat(qmc_context ctx, qmc_stream stream,
  *   nus_seeds, shifts: device [s] u32, or NULL.
  *   out_u32, out_f32: device, dimension-major with leading dimension ld >= n; either may be
  *              NULL but not both.  Outputs must not overlap each other or the inputs.
- *   flags:     0 or QMC_SHIFT_XOR.
+ *   flags:     0, QMC_SHIFT_XOR, QMC_POINT_MAJOR (point-major layout: out[(i-first)*ld + j] with
+ *              ld >= s; then an output spans ((n-1)*ld + s) words).
  * Errors: INVALID_ARGUMENT (NULL inputs, both outputs NULL, ld < n, unknown flags),
  *         OUT_OF_RANGE (s == 0 or s > QMC_MAX_DIMS, first + n > 2^32). n == 0 is a no-op. */
 qmc_status qmc_generate_sobol(qmc_context ctx, qmc_stream stream,
@@ -152,7 +155,8 @@ qmc_status qmc_generate_sobol(qmc_context ctx, qmc_stream stream,
  *     v = v + shifts[j] mod 2^32 if shifts != NULL (v ^ shifts[j] with QMC_SHIFT_XOR)
  *     outputs as for qmc_generate_sobol.
  *   generator: device [s] u32 (odd components give a Latin hypercube at 2^m points).
- * Errors as for qmc_generate_sobol; flags may combine QMC_SHIFT_XOR and QMC_LATTICE_BACKWARD. */
+ * Errors as for qmc_generate_sobol; flags may combine QMC_SHIFT_XOR, QMC_LATTICE_BACKWARD and
+ * QMC_POINT_MAJOR. */
 qmc_status qmc_generate_lattice(qmc_context ctx, qmc_stream stream,
                                 const uint32_t* generator, uint32_t s,
                                 uint64_t first, uint64_t n,

@@ -26,6 +26,7 @@ from ._lib import (  # noqa: F401
     QMC_PIXEL_NUS,
     QMC_PIXEL_RANDOM_GENERATOR,
     QMC_PIXEL_SHIFT,
+    QMC_POINT_MAJOR,
     QMC_SAMPLER_LATTICE,
     QMC_SAMPLER_POINTS,
     QMC_SAMPLER_SOBOL,
@@ -141,15 +142,18 @@ def _check_len(t, s, name):
         raise ValueError("%s needs at least %d entries" % (name, s))
 
 
-def _outputs(s, n, ld, out_u32, out_f32, want_u32, want_f32, device):
+def _outputs(s, n, ld, out_u32, out_f32, want_u32, want_f32, device, point_major=False):
+    """Output tensors: [s][ld] (dimension-major) or [n][ld] (point-major, ld >= s)."""
     torch = _torch()
-    ld = n if ld is None else ld
+    ld = (s if point_major else n) if ld is None else ld
+    shape = (n, ld) if point_major else (s, ld)
     if out_u32 is None and want_u32:
-        out_u32 = torch.empty((s, ld), dtype=torch.int32, device=device)
+        out_u32 = torch.empty(shape, dtype=torch.int32, device=device)
     if out_f32 is None and want_f32:
-        out_f32 = torch.empty((s, ld), dtype=torch.float32, device=device)
+        out_f32 = torch.empty(shape, dtype=torch.float32, device=device)
+    need = (n - 1) * ld + s if point_major else (s - 1) * ld + n
     for t, name in ((out_u32, "out_u32"), (out_f32, "out_f32")):
-        if t is not None and t.numel() < (s - 1) * ld + n:
+        if t is not None and t.numel() < need:
             raise ValueError("%s is too small for s=%d, ld=%d, n=%d" % (name, s, ld, n))
     return ld, out_u32, out_f32
 
@@ -158,7 +162,7 @@ def qmc_generate_sobol(matrices, first, n, nus_seeds=None, shifts=None, flags=0,
                        ld=None, want_u32=True, want_f32=True):
     """Points i in [first, first+n) of the digital sequence with device matrices [s][32].
 
-    Returns (u32 int32 tensor [s][ld] or None, float32 tensor [s][ld] or None).
+    Returns (u32 int32 tensor, float32 tensor), each [s][ld] ([n][ld] with QMC_POINT_MAJOR) or None.
     """
     torch = _torch()
     s = matrices.shape[0]
@@ -166,7 +170,8 @@ def qmc_generate_sobol(matrices, first, n, nus_seeds=None, shifts=None, flags=0,
         raise ValueError("matrices must have shape [s][32]")
     _check_len(nus_seeds, s, "nus_seeds")
     _check_len(shifts, s, "shifts")
-    ld, out_u32, out_f32 = _outputs(s, n, ld, out_u32, out_f32, want_u32, want_f32, matrices.device)
+    ld, out_u32, out_f32 = _outputs(s, n, ld, out_u32, out_f32, want_u32, want_f32, matrices.device,
+                                    bool(flags & QMC_POINT_MAJOR))
     st = load().qmc_generate_sobol(
         context(matrices.device), _stream(), _dev_ptr(matrices, "matrices", _u32_types()), s, first, n,
         _dev_ptr(nus_seeds, "nus_seeds", _u32_types()), _dev_ptr(shifts, "shifts", _u32_types()), flags,
@@ -183,7 +188,8 @@ def qmc_generate_lattice(generator, first, n, shifts=None, flags=0, out_u32=None
     if generator.dim() != 1:
         raise ValueError("generator must be a vector [s]")
     _check_len(shifts, s, "shifts")
-    ld, out_u32, out_f32 = _outputs(s, n, ld, out_u32, out_f32, want_u32, want_f32, generator.device)
+    ld, out_u32, out_f32 = _outputs(s, n, ld, out_u32, out_f32, want_u32, want_f32, generator.device,
+                                    bool(flags & QMC_POINT_MAJOR))
     st = load().qmc_generate_lattice(
         context(generator.device), _stream(), _dev_ptr(generator, "generator", _u32_types()), s, first, n,
         _dev_ptr(shifts, "shifts", _u32_types()), flags,

@@ -20,6 +20,7 @@ QMC_MAX_DIMS = 64
 QMC_MAX_DEGREE = 16
 QMC_SHIFT_XOR = 1
 QMC_LATTICE_BACKWARD = 2
+QMC_POINT_MAJOR = 128
 QMC_PIXEL_NUS = 4
 QMC_PIXEL_SHIFT = 8
 QMC_PIXEL_RANDOM_GENERATOR = 16

@@ -264,6 +264,70 @@ __global__ __launch_bounds__(kBlock) void lattice_general(const uint32_t* __rest
 }
 
 
+// ------------------------------------------------------------ point-major ----
+//
+// out[(i - first) * ld + j]: a wavefront takes 64 consecutive points, forms the s components
+// of its lane's point one dimension at a time into an LDS tile, then writes the tile row by
+// row, so every store covers one point's s consecutive words.
+
+template <bool NUS, bool SHIFT, bool SXOR, bool WU, bool WF>
+__global__ __launch_bounds__(kWave) void sobol_point_major(const uint32_t* __restrict__ mats, uint32_t s,
+                                                           uint32_t first, uint32_t n,
+                                                           const uint32_t* __restrict__ seeds,
+                                                           const uint32_t* __restrict__ shifts,
+                                                           uint32_t* __restrict__ ou, float* __restrict__ of,
+                                                           uint64_t ld) {
+    dev::set_fp32_round_toward_zero();
+    __shared__ SobolLds L;
+    __shared__ uint32_t tile[kWave][QMC_MAX_DIMS + 1];
+    stage_sobol<NUS, SHIFT>(L, mats, s, seeds, shifts);
+    const uint32_t lane = threadIdx.x;
+    for (uint32_t o0 = blockIdx.x * kWave; o0 < n; o0 += gridDim.x * kWave) {
+        const uint32_t i = first + o0 + lane;
+        for (uint32_t j = 0; j < s; ++j) {
+            uint32_t v = matrix_product(L.cols[j], i);
+            if constexpr (NUS) v = dev::nus_from_mirrored(v, L.seed[j], L.sm[j]);
+            if constexpr (SHIFT) v = dev::apply_shift<SXOR>(v, L.shift[j]);
+            tile[lane][j] = v;
+        }
+        __syncthreads();
+        const uint32_t rows = min(n - o0, kWave);
+        for (uint32_t r = 0; r < rows; ++r) {
+            if (lane < s) {
+                const uint32_t v = tile[r][lane];
+                const uint64_t at = uint64_t(o0 + r) * ld + lane;
+                if constexpr (WU) ou[at] = v;
+                if constexpr (WF) of[at] = dev::u32_to_unifloat_rtz(v);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <bool BACK, bool SHIFT, bool SXOR, bool WU, bool WF>
+__global__ __launch_bounds__(kWave) void lattice_point_major(const uint32_t* __restrict__ gen, uint32_t s,
+                                                             uint32_t first, uint32_t n,
+                                                             const uint32_t* __restrict__ shifts,
+                                                             uint32_t* __restrict__ ou, float* __restrict__ of,
+                                                             uint64_t ld) {
+    dev::set_fp32_round_toward_zero();
+    __shared__ LatticeLds L;
+    stage_lattice<SHIFT>(L, gen, s, shifts);
+    const uint32_t lane = threadIdx.x;
+    // lane l writes component l of each point: the stores of one point are s consecutive words
+    if (lane >= s) return;
+    const uint32_t g = L.g[lane];
+    const uint32_t sh = SHIFT ? L.shift[lane] : 0u;
+    for (uint32_t o = blockIdx.x * kWave; o < min(n, blockIdx.x * kWave + kWave); ++o) {
+        const uint32_t i = first + o;
+        uint32_t v = dev::brev(BACK ? ~i : i) * g;
+        if constexpr (SHIFT) v = dev::apply_shift<SXOR>(v, sh);
+        const uint64_t at = uint64_t(o) * ld + lane;
+        if constexpr (WU) ou[at] = v;
+        if constexpr (WF) of[at] = dev::u32_to_unifloat_rtz(v);
+    }
+}
+
 // ------------------------------------------------------------------ Halton ----
 //
 // Radical inversion in prime bases (Sec. 2.2): component j of point i is
@@ -499,10 +563,14 @@ qmc_status validate_generation(const char* who, qmc_context ctx, const void* tab
     if (n == 0) return QMC_OK;
     if (!table) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: table pointer is NULL", who);
     if (!ou && !of) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: both outputs are NULL", who);
-    if (ld < n) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: ld (%llu) < n (%llu)", who, (unsigned long long)ld,
-                            (unsigned long long)n);
-    if (ld > (uint64_t(1) << 56) / s) return fail(QMC_ERR_OUT_OF_RANGE, "%s: ld too large", who);
-    const uint64_t out_bytes = ((uint64_t(s) - 1) * ld + n) * 4;
+    const bool pm = (flags & QMC_POINT_MAJOR) != 0;
+    if (!pm && ld < n)
+        return fail(QMC_ERR_INVALID_ARGUMENT, "%s: ld (%llu) < n (%llu)", who, (unsigned long long)ld,
+                    (unsigned long long)n);
+    if (pm && ld < s)
+        return fail(QMC_ERR_INVALID_ARGUMENT, "%s: point-major ld (%llu) < s (%u)", who, (unsigned long long)ld, s);
+    if (ld > (uint64_t(1) << 56) / (pm ? n : s)) return fail(QMC_ERR_OUT_OF_RANGE, "%s: ld too large", who);
+    const uint64_t out_bytes = (pm ? (n - 1) * ld + s : (uint64_t(s) - 1) * ld + n) * 4;
     if (ranges_overlap(ou, out_bytes, of, out_bytes))
         return fail(QMC_ERR_INVALID_ARGUMENT, "%s: outputs overlap", who);
     const void* ins[3] = {table, aux0, aux1};
@@ -536,15 +604,16 @@ extern "C" qmc_status qmc_generate_sobol(qmc_context ctx, qmc_stream stream, con
                                          const uint32_t* shifts, uint32_t flags, uint32_t* out_u32, float* out_f32,
                                          uint64_t ld) {
     const char* who = "qmc_generate_sobol";
-    qmc_status st = validate_generation(who, ctx, matrices, 128, s, first, n, flags, QMC_SHIFT_XOR, nus_seeds, shifts,
-                                        out_u32, out_f32, ld);
+    qmc_status st = validate_generation(who, ctx, matrices, 128, s, first, n, flags, QMC_SHIFT_XOR | QMC_POINT_MAJOR,
+                                        nus_seeds, shifts, out_u32, out_f32, ld);
     if (st != QMC_OK || n == 0) return st;
+    const bool pm = (flags & QMC_POINT_MAJOR) != 0;
     if (n > (uint64_t(1) << 31)) {  // kernels count indices in 32 bits: split [0, 2^32)
-        const uint64_t h = uint64_t(1) << 31;
+        const uint64_t h = uint64_t(1) << 31, step = pm ? h * ld : h;
         st = qmc_generate_sobol(ctx, stream, matrices, s, first, h, nus_seeds, shifts, flags, out_u32, out_f32, ld);
         if (st != QMC_OK) return st;
         return qmc_generate_sobol(ctx, stream, matrices, s, first + h, n - h, nus_seeds, shifts, flags,
-                                  out_u32 ? out_u32 + h : nullptr, out_f32 ? out_f32 + h : nullptr, ld);
+                                  out_u32 ? out_u32 + step : nullptr, out_f32 ? out_f32 + step : nullptr, ld);
     }
     DeviceGuard guard(ctx->device);
     if (guard.status != QMC_OK) return guard.status;
@@ -558,7 +627,13 @@ extern "C" qmc_status qmc_generate_sobol(qmc_context ctx, qmc_stream stream, con
         with_bool(shift, [&](auto SH) {
             with_bool(sxor && shift, [&](auto SX) {
                 with_outputs(out_u32 != nullptr, out_f32 != nullptr, [&](auto WU, auto WF) {
-                    if (fast) {
+                    if (pm) {
+                        const uint64_t want = (n + kWave - 1) / kWave;
+                        const uint32_t gx = static_cast<uint32_t>(std::min<uint64_t>(want, uint64_t(ctx->num_cus) * 32));
+                        hipLaunchKernelGGL((sobol_point_major<NUS.value, SH.value, SX.value, WU.value, WF.value>),
+                                           dim3(gx), dim3(kWave), 0, hs, matrices, s, first32, nn, nus_seeds, shifts,
+                                           out_u32, out_f32, ld);
+                    } else if (fast) {
                         with_bool(ctx->sobol_tune.nontemporal != 0, [&](auto NT) {
                             uint32_t nchunks;
                             const GenTune& tn = ctx->sobol_tune;
@@ -584,14 +659,16 @@ extern "C" qmc_status qmc_generate_lattice(qmc_context ctx, qmc_stream stream, c
                                            uint32_t* out_u32, float* out_f32, uint64_t ld) {
     const char* who = "qmc_generate_lattice";
     qmc_status st = validate_generation(who, ctx, generator, 4, s, first, n, flags,
-                                        QMC_SHIFT_XOR | QMC_LATTICE_BACKWARD, shifts, nullptr, out_u32, out_f32, ld);
+                                        QMC_SHIFT_XOR | QMC_LATTICE_BACKWARD | QMC_POINT_MAJOR, shifts, nullptr,
+                                        out_u32, out_f32, ld);
     if (st != QMC_OK || n == 0) return st;
+    const bool pm = (flags & QMC_POINT_MAJOR) != 0;
     if (n > (uint64_t(1) << 31)) {  // kernels count indices in 32 bits: split [0, 2^32)
-        const uint64_t h = uint64_t(1) << 31;
+        const uint64_t h = uint64_t(1) << 31, step = pm ? h * ld : h;
         st = qmc_generate_lattice(ctx, stream, generator, s, first, h, shifts, flags, out_u32, out_f32, ld);
         if (st != QMC_OK) return st;
         return qmc_generate_lattice(ctx, stream, generator, s, first + h, n - h, shifts, flags,
-                                    out_u32 ? out_u32 + h : nullptr, out_f32 ? out_f32 + h : nullptr, ld);
+                                    out_u32 ? out_u32 + step : nullptr, out_f32 ? out_f32 + step : nullptr, ld);
     }
     DeviceGuard guard(ctx->device);
     if (guard.status != QMC_OK) return guard.status;
@@ -606,7 +683,11 @@ extern "C" qmc_status qmc_generate_lattice(qmc_context ctx, qmc_stream stream, c
         with_bool(shift, [&](auto SH) {
             with_bool(sxor && shift, [&](auto SX) {
                 with_outputs(out_u32 != nullptr, out_f32 != nullptr, [&](auto WU, auto WF) {
-                    if (fast) {
+                    if (pm) {
+                        hipLaunchKernelGGL((lattice_point_major<BK.value, SH.value, SX.value, WU.value, WF.value>),
+                                           dim3(static_cast<uint32_t>((n + kWave - 1) / kWave)), dim3(kWave), 0, hs,
+                                           generator, s, first32, nn, shifts, out_u32, out_f32, ld);
+                    } else if (fast) {
                         with_bool(ctx->lattice_tune.nontemporal != 0, [&](auto NT) {
                             uint32_t nchunks;
                             const GenTune& tn = ctx->lattice_tune;

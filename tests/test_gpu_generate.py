@@ -226,3 +226,38 @@ def test_autotune_generate_reports_candidates(qmc):
     assert len(lines) == 8 and all('"ms"' in l for l in lines)
     gu, gf, eu, ef = _run_sobol(qmc, 8, 0, 70000, True, True)
     assert np.array_equal(gu, eu) and np.array_equal(gf, ef)
+
+
+@pytest.mark.parametrize("kind,s,first,n,flags,ld", [
+    ("sobol", 32, 0, 5000, 0, None),
+    ("sobol", 7, 4 * 33, 1001, XOR, 9),
+    ("sobol", 64, (1 << 32) - 300, 300, 0, None),
+    ("lattice", 32, 0, 5000, BACK, None),
+    ("lattice", 5, 13, 777, XOR, 8),
+])
+def test_point_major_layout(qmc, kind, s, first, n, flags, ld):
+    """out[(i - first) * ld + j] against the oracle, bit for bit, and nothing written between
+    rows when ld > s."""
+    import torch
+
+    pm = qmc.QMC_POINT_MAJOR
+    ldv = s if ld is None else ld
+    out_u = torch.full((n, ldv), 7, dtype=torch.int32, device="cuda")
+    out_f = torch.full((n, ldv), 2.0, dtype=torch.float32, device="cuda")
+    if kind == "sobol":
+        m = _mats(s)
+        qmc.qmc_generate_sobol(qmc.from_u32(m), first, n, qmc.from_u32(nus_seeds(s, 1)), qmc.from_u32(cp_shifts(s, 2)),
+                               flags | pm, out_u32=out_u, out_f32=out_f, ld=ldv)
+        eu, ef = generate.generate_sobol(m, first, n, nus_seeds(s, 1), cp_shifts(s, 2), flags)
+    else:
+        g = lattice_vector(s, 20, 3)
+        qmc.qmc_generate_lattice(qmc.from_u32(g), first, n, qmc.from_u32(cp_shifts(s, 2)), flags | pm, out_u32=out_u,
+                                 out_f32=out_f, ld=ldv)
+        eu, ef = generate.generate_lattice(g, first, n, cp_shifts(s, 2), flags)
+    torch.cuda.synchronize()
+    gu = qmc.to_u32(out_u)
+    gf = out_f.cpu().numpy().view(np.uint32)
+    assert np.array_equal(gu[:, :s], eu.T)
+    assert np.array_equal(gf[:, :s], ef.view(np.uint32).T)
+    if ldv > s:
+        assert (gu[:, s:] == 7).all() and (out_f[:, s:] == 2.0).all().item()
