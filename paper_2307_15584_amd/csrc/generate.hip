@@ -270,7 +270,11 @@ __global__ __launch_bounds__(kBlock) void lattice_general(const uint32_t* __rest
 // of its lane's point one dimension at a time into an LDS tile, then writes the tile row by
 // row, so every store covers one point's s consecutive words.
 
-template <bool NUS, bool SHIFT, bool SXOR, bool WU, bool WF>
+// The point of index i = 64 h + lane (first a multiple of 64) is the XOR of a part from the
+// high index bits, the same for the whole wavefront (lanes 6..31 select a column each, XOR
+// reduction in DPP), and a part from the lane's six low bits; other starts use the plain
+// matrix product.
+template <bool NUS, bool SHIFT, bool SXOR, bool WU, bool WF, bool SPLIT>
 __global__ __launch_bounds__(kWave) void sobol_point_major(const uint32_t* __restrict__ mats, uint32_t s,
                                                            uint32_t first, uint32_t n,
                                                            const uint32_t* __restrict__ seeds,
@@ -282,20 +286,34 @@ __global__ __launch_bounds__(kWave) void sobol_point_major(const uint32_t* __res
     __shared__ uint32_t tile[kWave][QMC_MAX_DIMS + 1];
     stage_sobol<NUS, SHIFT>(L, mats, s, seeds, shifts);
     const uint32_t lane = threadIdx.x;
+    const uint32_t k32 = lane & 31u;
     for (uint32_t o0 = blockIdx.x * kWave; o0 < n; o0 += gridDim.x * kWave) {
         const uint32_t i = first + o0 + lane;
+        const uint32_t h = (first + o0) >> 6;
         for (uint32_t j = 0; j < s; ++j) {
-            uint32_t v = matrix_product(L.cols[j], i);
+            uint32_t v;
+            if constexpr (SPLIT) {
+                const uint32_t part = half_wave_xor((k32 >= 6u && ((h >> (k32 - 6u)) & 1u)) ? L.cols[j][k32] : 0u);
+                v = __builtin_amdgcn_readlane(part, 31);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) v ^= (0u - ((lane >> k) & 1u)) & L.cols[j][k];
+            } else {
+                v = matrix_product(L.cols[j], i);
+            }
             if constexpr (NUS) v = dev::nus_from_mirrored(v, L.seed[j], L.sm[j]);
             if constexpr (SHIFT) v = dev::apply_shift<SXOR>(v, L.shift[j]);
             tile[lane][j] = v;
         }
         __syncthreads();
         const uint32_t rows = min(n - o0, kWave);
-        for (uint32_t r = 0; r < rows; ++r) {
-            if (lane < s) {
-                const uint32_t v = tile[r][lane];
-                const uint64_t at = uint64_t(o0 + r) * ld + lane;
+        // two rows per store instruction when a row fits half a wavefront
+        const uint32_t per = s <= 32 ? 2u : 1u;
+        const uint32_t sub = s <= 32 ? (lane >> 5) : 0u, col = s <= 32 ? k32 : lane;
+        for (uint32_t r0 = 0; r0 < rows; r0 += per) {
+            const uint32_t r = r0 + sub;
+            if (col < s && r < rows) {
+                const uint32_t v = tile[r][col];
+                const uint64_t at = uint64_t(o0 + r) * ld + col;
                 if constexpr (WU) ou[at] = v;
                 if constexpr (WF) of[at] = dev::u32_to_unifloat_rtz(v);
             }
@@ -630,9 +648,12 @@ extern "C" qmc_status qmc_generate_sobol(qmc_context ctx, qmc_stream stream, con
                     if (pm) {
                         const uint64_t want = (n + kWave - 1) / kWave;
                         const uint32_t gx = static_cast<uint32_t>(std::min<uint64_t>(want, uint64_t(ctx->num_cus) * 32));
-                        hipLaunchKernelGGL((sobol_point_major<NUS.value, SH.value, SX.value, WU.value, WF.value>),
-                                           dim3(gx), dim3(kWave), 0, hs, matrices, s, first32, nn, nus_seeds, shifts,
-                                           out_u32, out_f32, ld);
+                        with_bool(first % kWave == 0, [&](auto SPLIT) {
+                            hipLaunchKernelGGL(
+                                (sobol_point_major<NUS.value, SH.value, SX.value, WU.value, WF.value, SPLIT.value>),
+                                dim3(gx), dim3(kWave), 0, hs, matrices, s, first32, nn, nus_seeds, shifts, out_u32,
+                                out_f32, ld);
+                        });
                     } else if (fast) {
                         with_bool(ctx->sobol_tune.nontemporal != 0, [&](auto NT) {
                             uint32_t nchunks;

@@ -232,6 +232,8 @@ def test_autotune_generate_reports_candidates(qmc):
     ("sobol", 32, 0, 5000, 0, None),
     ("sobol", 7, 4 * 33, 1001, XOR, 9),
     ("sobol", 64, (1 << 32) - 300, 300, 0, None),
+    ("sobol", 40, 64 * 1000, 3000, XOR, 45),     # start on a multiple of 64: split index product
+    ("sobol", 3, (1 << 32) - 64 * 40, 64 * 40, 0, None),
     ("lattice", 32, 0, 5000, BACK, None),
     ("lattice", 5, 13, 777, XOR, 8),
 ])
