@@ -21,6 +21,8 @@ Modules:
               (Eq. PixelShiftedR1LS)
   halton      radical inversion in prime bases with identity, Faure or linear digit
               permutations, and the Halton sequence (Sec. 2.2)
+  partition   64-bit indices (wide Sobol' matrices, 64-digit lattice) and the partitioned
+              enumeration of one sequence across processing elements (Sec. 2.5.1)
   integrands  Genz and Gaussian-lobe integrands and their parameter gradients
   estimator   per-pixel QMC integro-approximation, loss, analytic and
               finite-difference gradients (Sec. 2.5)
