@@ -518,6 +518,18 @@ def main():
     out["sobol_point_major_2p24x32"] = {"kernel_ms": round(pm_ms, 4),
                                         "gpts_dim_per_s": round(s * n / (pm_ms * 1e-3) / 1e9, 1),
                                         "hbm_frac": round(alg_bytes / (pm_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    # 64-bit indices and partitioned enumeration: part 77 of 2^8 from m = 2^44 (global indices
+    # near 2^52), the same 2^24 x 32 scrambled + rotated workload as the headline kernel
+    wide = q.from_u32(q.qmc_sobol_matrices_wide(s, sobol_direction_init(s, 0), 64))
+    w_ms = _event_ms(torch, lambda: q.qmc_generate_sobol64(wide, 1 << 44, n, 8, 77, seeds, shifts, 0, out_u32=su,
+                                                            out_f32=sf), 10)
+    l64_ms = _event_ms(torch, lambda: q.qmc_generate_lattice64(gvec, 1 << 44, n, 8, 77, shifts, 0, out_u32=su,
+                                                                out_f32=sf), 10)
+    out["partitioned_64bit_2p24x32"] = {
+        "sobol_kernel_ms": round(w_ms, 4), "sobol_hbm_frac": round(alg_bytes / (w_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "lattice_kernel_ms": round(l64_ms, 4),
+        "lattice_hbm_frac": round(alg_bytes / (l64_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "note": "part 77 of 2^8, subsequence indices from 2^44; cost of 64-bit indices = ratio to the 32-bit kernels"}
     m4 = q.from_u32(q.qmc_sobol_matrices(4, sobol_direction_init(4, 0)))
     c1u = torch.empty((4, 1 << 16), dtype=torch.int32, device="cuda")
     c1f = torch.empty((4, 1 << 16), dtype=torch.float32, device="cuda")

@@ -90,6 +90,15 @@ qmc_status qmc_primitive_polynomials(uint32_t count, uint32_t* codes);
  * or s == 0, or a polynomial degree above QMC_MAX_DEGREE). */
 qmc_status qmc_sobol_matrices(uint32_t s, const uint32_t* direction_init, uint32_t* matrices);
 
+/* The same matrices for indices of up to `columns` bits (the 64-bit index form of Alg. 3),
+ * written to host array matrices[s][columns]: column k (= matrices[j*columns+k]) keeps the top
+ * 32 digits of the fraction m_(k+1) 2^-(k+1), i.e. m_(k+1) << (31-k) for k < 32 and
+ * m_(k+1) >> (k-31) for k >= 32; dimension 0 has zero columns from 32 on.  The first 32
+ * columns equal qmc_sobol_matrices'.  columns: 1..64.  Errors as for qmc_sobol_matrices,
+ * plus OUT_OF_RANGE for columns outside [1, 64]. */
+qmc_status qmc_sobol_matrices_wide(uint32_t s, const uint32_t* direction_init, uint32_t columns,
+                                   uint32_t* matrices);
+
 /* ------------------------------------------------------------- generation ---- */
 
 /* Halton sequence (Sec. 2.2): component j of point i is
@@ -162,6 +171,45 @@ qmc_status qmc_generate_lattice(qmc_context ctx, qmc_stream stream,
                                 uint64_t first, uint64_t n,
                                 const uint32_t* shifts, uint32_t flags,
                                 uint32_t* out_u32, float* out_f32, uint64_t ld);
+
+/* 64-bit indices and partitioned enumeration (Sec. 2.5.1; the 64-bit index of Alg. 3).
+ * One sequence is split among 2^log2_parts processing elements by an extra splitting
+ * dimension, the van der Corput sequence phi_2(i): part p receives, in index order, the
+ * indices whose phi_2 lies in [p 2^-q, (p+1) 2^-q) (q = log2_parts), which are exactly
+ *     i(m) = m 2^q + rev_q(p),   m = 0, 1, 2, ...      (rev_q mirrors the q low bits)
+ * These calls write points m in [first, first+n) of part p, dimension-major as
+ * qmc_generate_sobol: out[j*ld + (m-first)].  q = 0 (one part, p = 0) gives the sequence
+ * itself with 64-bit indices i = m.
+ *
+ * Digital sequence: v = C_j a(i) over all `columns` index bits with matrices [s][columns]
+ * from qmc_sobol_matrices_wide (any matrices allowed); then NUS, shift and conversion exactly
+ * as qmc_generate_sobol.  Every index must be below 2^columns:
+ *     first + n <= 2^(columns - q), else OUT_OF_RANGE (no index bit is dropped silently).
+ *   columns:    1..64;  log2_parts: 0..min(32, columns);  part < 2^log2_parts.
+ *   flags:      0 or QMC_SHIFT_XOR (QMC_POINT_MAJOR is not available here).
+ * Errors: as qmc_generate_sobol, with OUT_OF_RANGE for columns, log2_parts, part and the
+ * index range above.  n may exceed 2^32 (the output then spans more than 16 GiB). */
+qmc_status qmc_generate_sobol64(qmc_context ctx, qmc_stream stream,
+                                const uint32_t* matrices, uint32_t columns, uint32_t s,
+                                uint32_t log2_parts, uint32_t part,
+                                uint64_t first, uint64_t n,
+                                const uint32_t* nus_seeds, const uint32_t* shifts,
+                                uint32_t flags,
+                                uint32_t* out_u32, float* out_f32, uint64_t ld);
+
+/* Rank-1 lattice sequence with 64-bit indices (Eq. R1LS over all 64 binary digits):
+ *     v = floor(2^32 frac(phi_2(i) g_j)) = ((brev64(i) g_j) mod 2^64) >> 32
+ * (phi_2(2^64-1-i) with QMC_LATTICE_BACKWARD), then shift and conversion as
+ * qmc_generate_lattice, over the indices i(m) of part p above.  For i < 2^32 the value equals
+ * qmc_generate_lattice's forward one.  Index range: first + n <= 2^(64 - q).
+ *   flags: QMC_SHIFT_XOR, QMC_LATTICE_BACKWARD.
+ * Errors: as qmc_generate_sobol64. */
+qmc_status qmc_generate_lattice64(qmc_context ctx, qmc_stream stream,
+                                  const uint32_t* generator, uint32_t s,
+                                  uint32_t log2_parts, uint32_t part,
+                                  uint64_t first, uint64_t n,
+                                  const uint32_t* shifts, uint32_t flags,
+                                  uint32_t* out_u32, float* out_f32, uint64_t ld);
 
 /* ------------------------------------------------- per-pixel integration ---- */
 /*

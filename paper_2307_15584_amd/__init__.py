@@ -122,6 +122,18 @@ def qmc_sobol_matrices(s, direction_init):
     return out
 
 
+def qmc_sobol_matrices_wide(s, direction_init, columns):
+    """Sobol' generator matrices uint32 [s][columns] (host numpy) for indices of up to
+    `columns` <= 64 bits; the first 32 columns equal qmc_sobol_matrices'."""
+    di = np.ascontiguousarray(np.asarray(direction_init, dtype=np.uint32))
+    if di.shape != (s, QMC_MAX_DEGREE):
+        raise ValueError("direction_init must have shape (%d, %d)" % (s, QMC_MAX_DEGREE))
+    out = np.zeros((s, max(int(columns), 1)), dtype=np.uint32)
+    check(load().qmc_sobol_matrices_wide(s, di.ctypes.data_as(ctypes.c_void_p), columns,
+                                         out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
 # ------------------------------------------------------------- generation (device) ----
 
 def qmc_map_u32_to_unifloat(inp, out=None):
@@ -193,6 +205,44 @@ def qmc_generate_lattice(generator, first, n, shifts=None, flags=0, out_u32=None
     st = load().qmc_generate_lattice(
         context(generator.device), _stream(), _dev_ptr(generator, "generator", _u32_types()), s, first, n,
         _dev_ptr(shifts, "shifts", _u32_types()), flags,
+        _dev_ptr(out_u32, "out_u32", _u32_types()), _dev_ptr(out_f32, "out_f32", (torch.float32,)), ld)
+    check(st)
+    return out_u32, out_f32
+
+
+def qmc_generate_sobol64(matrices, first, n, log2_parts=0, part=0, nus_seeds=None, shifts=None, flags=0,
+                         out_u32=None, out_f32=None, ld=None, want_u32=True, want_f32=True):
+    """Points m in [first, first+n) of part `part` of 2^log2_parts (global index
+    m 2^log2_parts + rev(part)) of the digital sequence with device matrices [s][columns],
+    64-bit indices.  Returns (u32 int32 tensor [s][ld] or None, float32 tensor or None)."""
+    torch = _torch()
+    if matrices.dim() != 2:
+        raise ValueError("matrices must have shape [s][columns]")
+    s, columns = matrices.shape
+    _check_len(nus_seeds, s, "nus_seeds")
+    _check_len(shifts, s, "shifts")
+    ld, out_u32, out_f32 = _outputs(s, n, ld, out_u32, out_f32, want_u32, want_f32, matrices.device)
+    st = load().qmc_generate_sobol64(
+        context(matrices.device), _stream(), _dev_ptr(matrices, "matrices", _u32_types()), columns, s, log2_parts,
+        part, first, n, _dev_ptr(nus_seeds, "nus_seeds", _u32_types()), _dev_ptr(shifts, "shifts", _u32_types()),
+        flags, _dev_ptr(out_u32, "out_u32", _u32_types()), _dev_ptr(out_f32, "out_f32", (torch.float32,)), ld)
+    check(st)
+    return out_u32, out_f32
+
+
+def qmc_generate_lattice64(generator, first, n, log2_parts=0, part=0, shifts=None, flags=0, out_u32=None,
+                           out_f32=None, ld=None, want_u32=True, want_f32=True):
+    """Points m in [first, first+n) of part `part` of 2^log2_parts of the rank-1 lattice
+    sequence with device generator [s], 64-bit indices."""
+    torch = _torch()
+    if generator.dim() != 1:
+        raise ValueError("generator must be a vector [s]")
+    s = generator.shape[0]
+    _check_len(shifts, s, "shifts")
+    ld, out_u32, out_f32 = _outputs(s, n, ld, out_u32, out_f32, want_u32, want_f32, generator.device)
+    st = load().qmc_generate_lattice64(
+        context(generator.device), _stream(), _dev_ptr(generator, "generator", _u32_types()), s, log2_parts, part,
+        first, n, _dev_ptr(shifts, "shifts", _u32_types()), flags,
         _dev_ptr(out_u32, "out_u32", _u32_types()), _dev_ptr(out_f32, "out_f32", (torch.float32,)), ld)
     check(st)
     return out_u32, out_f32

@@ -72,6 +72,10 @@ SIGNATURES = {
     "qmc_generate_sobol": (_st, [_vp, _vp, _vp, _u32, _u64, _u64, _vp, _vp, _u32, _vp, _vp, _u64]),
     "qmc_generate_lattice": (_st, [_vp, _vp, _vp, _u32, _u64, _u64, _vp, _u32, _vp, _vp, _u64]),
     "qmc_generate_halton": (_st, [_vp, _vp, _u32, _u64, _u64, _u32, _vp, _vp, _vp, _u64]),
+    "qmc_sobol_matrices_wide": (_st, [_u32, _vp, _u32, _vp]),
+    "qmc_generate_sobol64": (_st, [_vp, _vp, _vp, _u32, _u32, _u32, _u32, _u64, _u64, _vp, _vp, _u32, _vp, _vp,
+                                   _u64]),
+    "qmc_generate_lattice64": (_st, [_vp, _vp, _vp, _u32, _u32, _u32, _u64, _u64, _vp, _u32, _vp, _vp, _u64]),
     "qmc_workspace_size": (_st, [_vp, _vp, _vp, _u32, _u32, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "qmc_integrate_pixels": (_st, [_vp, _vp, _vp, _vp, _u32, _u32, _vp, _u32, _u32, _vp, _vp, _vp,
                                    ctypes.c_size_t]),

@@ -264,6 +264,179 @@ __global__ __launch_bounds__(kBlock) void lattice_general(const uint32_t* __rest
 }
 
 
+// ------------------------------------------------ 64-bit indices, partitions ----
+//
+// Part p of 2^q receives the indices i = m 2^q + r, r = rev_q(p); the kernels enumerate m.
+// For a digital sequence, bit k of m selects column k + q, and the bits of r select a fixed
+// set of columns below q whose XOR is formed once per wavefront.  m has up to 64 bits, so
+// the chunk part takes a reduction over the whole wavefront (lanes 8..63 select columns
+// 8..63 of the subsequence), and a second one for chunk h + 1 when `first` is not a
+// multiple of 256.
+
+// XOR of v over all 64 lanes, as a wave-uniform value.
+__device__ __forceinline__ uint32_t wave_xor(uint32_t v) {
+    const uint32_t h = half_wave_xor(v);
+    return __builtin_amdgcn_readlane(h, 31) ^ __builtin_amdgcn_readlane(h, 63);
+}
+
+// Needs first % 4 == 0, ld % 4 == 0, 16-byte aligned outputs, n <= 2^31 and every m below
+// 2^(columns - q).
+template <bool NUS, bool SHIFT, bool SXOR, bool WU, bool WF, bool NT>
+__global__ __launch_bounds__(kWave) void sobol64_fast(const uint32_t* __restrict__ mats, uint32_t columns,
+                                                      uint32_t q, uint32_t r, uint64_t first, uint32_t n,
+                                                      const uint32_t* __restrict__ seeds,
+                                                      const uint32_t* __restrict__ shifts, uint32_t* __restrict__ ou,
+                                                      float* __restrict__ of, uint64_t ld, uint32_t cpw,
+                                                      uint32_t nchunks) {
+    dev::set_fp32_round_toward_zero();
+    const uint32_t j = blockIdx.y;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t cb = blockIdx.x * cpw;
+    const uint32_t ce = min(cb + cpw, nchunks);
+    const uint32_t* cj = mats + uint64_t(j) * columns;
+    uint32_t col = lane + q < columns ? cj[lane + q] : 0u;               // image of bit `lane` of m
+    uint32_t low = (lane < q && ((r >> lane) & 1u)) ? cj[lane] : 0u;     // bits of r
+    if constexpr (NUS) {
+        col = dev::brev(col);
+        low = dev::brev(low);
+    }
+    const uint32_t xr = wave_xor(low);
+    const uint32_t seed = NUS ? seeds[j] : 0u;
+    const uint32_t sm = dev::seed_multiplier(seed);
+    const uint32_t sh = SHIFT ? shifts[j] : 0u;
+    const uint32_t t = (static_cast<uint32_t>(first) & 255u) + 4u * lane;
+    const uint32_t carry = 0u - (t >> 8);
+    const bool straddle = (first & 255u) != 0;
+    uint32_t xlo = xr;
+#pragma unroll
+    for (int k = 2; k < 8; ++k) xlo ^= (0u - ((t >> k) & 1u)) & __builtin_amdgcn_readlane(col, k);
+    const uint32_t col0 = __builtin_amdgcn_readlane(col, 0), col1 = __builtin_amdgcn_readlane(col, 1);
+    const uint64_t hb = first >> 8;
+    const uint64_t base = uint64_t(j) * ld;
+    for (uint32_t c = cb; c < ce; ++c) {
+        const uint64_t h = hb + c;
+        const uint32_t sel = lane >= 8u ? static_cast<uint32_t>(h >> (lane - 8u)) & 1u : 0u;
+        uint32_t x = wave_xor(sel ? col : 0u);
+        if (straddle) {
+            const uint32_t sel1 = lane >= 8u ? static_cast<uint32_t>((h + 1u) >> (lane - 8u)) & 1u : 0u;
+            const uint32_t x1 = wave_xor(sel1 ? col : 0u);
+            x ^= (x ^ x1) & carry;
+        }
+        x ^= xlo;
+        uint32_t v0 = x, v1 = x ^ col0, v2 = x ^ col1, v3 = x ^ col0 ^ col1;
+        if constexpr (NUS) {
+            v0 = dev::nus_from_mirrored(v0, seed, sm);
+            v1 = dev::nus_from_mirrored(v1, seed, sm);
+            v2 = dev::nus_from_mirrored(v2, seed, sm);
+            v3 = dev::nus_from_mirrored(v3, seed, sm);
+        }
+        const uint32_t o = c * kChunk + 4u * lane;
+        if (o + 4u <= n)
+            emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, 4u, v0, v1, v2, v3, sh);
+        else if (o < n)
+            emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, n - o, v0, v1, v2, v3, sh);
+    }
+}
+
+struct Sobol64Lds {
+    uint32_t cols[QMC_MAX_DIMS][64];
+    uint32_t seed[QMC_MAX_DIMS];
+    uint32_t sm[QMC_MAX_DIMS];
+    uint32_t shift[QMC_MAX_DIMS];
+};
+
+// Any alignment: one index per thread, the plain product over all 64 index bits.
+template <bool NUS, bool SHIFT, bool SXOR, bool WU, bool WF>
+__global__ __launch_bounds__(kBlock) void sobol64_general(const uint32_t* __restrict__ mats, uint32_t columns,
+                                                          uint32_t s, uint32_t q, uint32_t r, uint64_t first,
+                                                          uint32_t n, const uint32_t* __restrict__ seeds,
+                                                          const uint32_t* __restrict__ shifts,
+                                                          uint32_t* __restrict__ ou, float* __restrict__ of,
+                                                          uint64_t ld) {
+    dev::set_fp32_round_toward_zero();
+    __shared__ Sobol64Lds L;
+    for (uint32_t t = threadIdx.x; t < s * 64; t += blockDim.x) {
+        const uint32_t k = t & 63u;
+        const uint32_t c = k < columns ? mats[uint64_t(t >> 6) * columns + k] : 0u;
+        L.cols[t >> 6][k] = NUS ? dev::brev(c) : c;
+    }
+    for (uint32_t t = threadIdx.x; t < s; t += blockDim.x) {
+        if constexpr (NUS) {
+            L.seed[t] = seeds[t];
+            L.sm[t] = dev::seed_multiplier(seeds[t]);
+        }
+        if constexpr (SHIFT) L.shift[t] = shifts[t];
+    }
+    __syncthreads();
+    for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < n; o += gridDim.x * kBlock) {
+        const uint64_t i = ((first + o) << q) | r;
+        const uint32_t ilo = static_cast<uint32_t>(i), ihi = static_cast<uint32_t>(i >> 32);
+        for (uint32_t j = 0; j < s; ++j) {
+            uint32_t v = matrix_product(L.cols[j], ilo) ^ matrix_product(L.cols[j] + 32, ihi);
+            if constexpr (NUS) v = dev::nus_from_mirrored(v, L.seed[j], L.sm[j]);
+            if constexpr (SHIFT) v = dev::apply_shift<SXOR>(v, L.shift[j]);
+            if constexpr (WU) ou[uint64_t(j) * ld + o] = v;
+            if constexpr (WF) of[uint64_t(j) * ld + o] = dev::u32_to_unifloat_rtz(v);
+        }
+    }
+}
+
+// floor(2^32 frac(phi_2(i) g)) for a 64-bit index: brev64(i) = brev(ilo) 2^32 + brev(ihi), and
+// the top word of its product with g modulo 2^64 is brev(ilo) g + high word of brev(ihi) g.
+__device__ __forceinline__ uint32_t lattice64_value(uint64_t i, uint32_t g) {
+    const uint32_t hi = dev::brev(static_cast<uint32_t>(i)), lo = dev::brev(static_cast<uint32_t>(i >> 32));
+    return hi * g + __umulhi(lo, g);
+}
+
+template <bool BACK, bool SHIFT, bool SXOR, bool WU, bool WF, bool NT>
+__global__ __launch_bounds__(kWave) void lattice64_fast(const uint32_t* __restrict__ gen, uint32_t q, uint32_t r,
+                                                        uint64_t first, uint32_t n,
+                                                        const uint32_t* __restrict__ shifts,
+                                                        uint32_t* __restrict__ ou, float* __restrict__ of, uint64_t ld,
+                                                        uint32_t cpw, uint32_t nchunks) {
+    dev::set_fp32_round_toward_zero();
+    const uint32_t j = blockIdx.y;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t cb = blockIdx.x * cpw;
+    const uint32_t ce = min(cb + cpw, nchunks);
+    const uint32_t g = gen[j];
+    const uint32_t sh = SHIFT ? shifts[j] : 0u;
+    const uint64_t base = uint64_t(j) * ld;
+    const uint64_t flip = BACK ? ~uint64_t(0) : 0u;
+    for (uint32_t c = cb; c < ce; ++c) {
+        const uint32_t o = c * kChunk + 4u * lane;
+        const uint64_t m = first + o;
+        const uint32_t v0 = lattice64_value(((m << q) | r) ^ flip, g);
+        const uint32_t v1 = lattice64_value((((m + 1u) << q) | r) ^ flip, g);
+        const uint32_t v2 = lattice64_value((((m + 2u) << q) | r) ^ flip, g);
+        const uint32_t v3 = lattice64_value((((m + 3u) << q) | r) ^ flip, g);
+        if (o + 4u <= n)
+            emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, 4u, v0, v1, v2, v3, sh);
+        else if (o < n)
+            emit4<SHIFT, SXOR, WU, WF, NT>(ou, of, base + o, n - o, v0, v1, v2, v3, sh);
+    }
+}
+
+template <bool BACK, bool SHIFT, bool SXOR, bool WU, bool WF>
+__global__ __launch_bounds__(kBlock) void lattice64_general(const uint32_t* __restrict__ gen, uint32_t s, uint32_t q,
+                                                            uint32_t r, uint64_t first, uint32_t n,
+                                                            const uint32_t* __restrict__ shifts,
+                                                            uint32_t* __restrict__ ou, float* __restrict__ of,
+                                                            uint64_t ld) {
+    dev::set_fp32_round_toward_zero();
+    __shared__ LatticeLds L;
+    stage_lattice<SHIFT>(L, gen, s, shifts);
+    for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < n; o += gridDim.x * kBlock) {
+        const uint64_t i = (((first + o) << q) | r) ^ (BACK ? ~uint64_t(0) : 0u);
+        for (uint32_t j = 0; j < s; ++j) {
+            uint32_t v = lattice64_value(i, L.g[j]);
+            if constexpr (SHIFT) v = dev::apply_shift<SXOR>(v, L.shift[j]);
+            if constexpr (WU) ou[uint64_t(j) * ld + o] = v;
+            if constexpr (WF) of[uint64_t(j) * ld + o] = dev::u32_to_unifloat_rtz(v);
+        }
+    }
+}
+
 // ------------------------------------------------------------ point-major ----
 //
 // out[(i - first) * ld + j]: a wavefront takes 64 consecutive points, forms the s components
@@ -569,13 +742,21 @@ bool ranges_overlap(const void* a, uint64_t abytes, const void* b, uint64_t bbyt
 }
 
 // Shared validation of the generation calls.
+// first + n <= 2^bits (bits <= 64).
+bool index_range_ok(uint64_t first, uint64_t n, uint32_t bits) {
+    if (bits >= 64) return n == 0 || n - 1 <= ~first;
+    const uint64_t lim = uint64_t(1) << bits;
+    return first <= lim && n <= lim - first;
+}
+
 qmc_status validate_generation(const char* who, qmc_context ctx, const void* table, uint64_t table_bytes_per_dim,
                                uint32_t s, uint64_t first, uint64_t n, uint32_t flags, uint32_t allowed_flags,
-                               const void* aux0, const void* aux1, const uint32_t* ou, const float* of, uint64_t ld) {
+                               const void* aux0, const void* aux1, const uint32_t* ou, const float* of, uint64_t ld,
+                               uint32_t index_bits = 32) {
     if (!ctx) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: context is NULL", who);
     if (s == 0 || s > QMC_MAX_DIMS) return fail(QMC_ERR_OUT_OF_RANGE, "%s: s = %u outside [1, %d]", who, s, QMC_MAX_DIMS);
-    if (first > (uint64_t(1) << 32) || n > (uint64_t(1) << 32) - first)
-        return fail(QMC_ERR_OUT_OF_RANGE, "%s: first + n exceeds 2^32 (first=%llu n=%llu)", who,
+    if (!index_range_ok(first, n, index_bits))
+        return fail(QMC_ERR_OUT_OF_RANGE, "%s: first + n exceeds 2^%u (first=%llu n=%llu)", who, index_bits,
                     (unsigned long long)first, (unsigned long long)n);
     if (flags & ~allowed_flags) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: unknown flags 0x%x", who, flags);
     if (n == 0) return QMC_OK;
@@ -588,6 +769,7 @@ qmc_status validate_generation(const char* who, qmc_context ctx, const void* tab
     if (pm && ld < s)
         return fail(QMC_ERR_INVALID_ARGUMENT, "%s: point-major ld (%llu) < s (%u)", who, (unsigned long long)ld, s);
     if (ld > (uint64_t(1) << 56) / (pm ? n : s)) return fail(QMC_ERR_OUT_OF_RANGE, "%s: ld too large", who);
+    if (!pm && n > (uint64_t(1) << 56)) return fail(QMC_ERR_OUT_OF_RANGE, "%s: n too large", who);
     const uint64_t out_bytes = (pm ? (n - 1) * ld + s : (uint64_t(s) - 1) * ld + n) * 4;
     if (ranges_overlap(ou, out_bytes, of, out_bytes))
         return fail(QMC_ERR_INVALID_ARGUMENT, "%s: outputs overlap", who);
@@ -723,6 +905,132 @@ extern "C" qmc_status qmc_generate_lattice(qmc_context ctx, qmc_stream stream, c
                                            dim3(general_grid(ctx, nn)), dim3(kBlock), 0, hs, generator, s, first32,
                                            nn, shifts, out_u32, out_f32, ld);
                     }
+                });
+            });
+        });
+    });
+    return check_launch(who);
+}
+
+namespace qmc {
+namespace {
+
+// Shared argument checks of the partitioned calls; sets *r = rev_q(part).
+qmc_status validate_partition(const char* who, uint32_t index_bits, uint32_t q, uint32_t part, uint32_t* r) {
+    if (q > 32 || q > index_bits)
+        return fail(QMC_ERR_OUT_OF_RANGE, "%s: log2_parts = %u outside [0, min(32, %u)]", who, q, index_bits);
+    if (q < 32 && part >> q)
+        return fail(QMC_ERR_OUT_OF_RANGE, "%s: part %u outside [0, 2^%u)", who, part, q);
+    uint32_t v = 0;
+    for (uint32_t k = 0; k < q; ++k) v |= ((part >> k) & 1u) << (q - 1 - k);
+    *r = v;
+    return QMC_OK;
+}
+
+// Runs launch(first, count, offset) over pieces of at most 2^31 points.
+template <typename F>
+void over_pieces(uint64_t first, uint64_t n, F&& launch) {
+    const uint64_t piece = uint64_t(1) << 31;
+    for (uint64_t done = 0; done < n; done += piece)
+        launch(first + done, static_cast<uint32_t>(std::min(piece, n - done)), done);
+}
+
+}  // namespace
+}  // namespace qmc
+
+extern "C" qmc_status qmc_generate_sobol64(qmc_context ctx, qmc_stream stream, const uint32_t* matrices,
+                                           uint32_t columns, uint32_t s, uint32_t log2_parts, uint32_t part,
+                                           uint64_t first, uint64_t n, const uint32_t* nus_seeds,
+                                           const uint32_t* shifts, uint32_t flags, uint32_t* out_u32,
+                                           float* out_f32, uint64_t ld) {
+    const char* who = "qmc_generate_sobol64";
+    if (columns == 0 || columns > 64)
+        return fail(QMC_ERR_OUT_OF_RANGE, "%s: columns = %u outside [1, 64]", who, columns);
+    uint32_t r = 0;
+    qmc_status st = validate_partition(who, columns, log2_parts, part, &r);
+    if (st != QMC_OK) return st;
+    st = validate_generation(who, ctx, matrices, uint64_t(columns) * 4, s, first, n, flags, QMC_SHIFT_XOR, nus_seeds,
+                             shifts, out_u32, out_f32, ld, columns - log2_parts);
+    if (st != QMC_OK || n == 0) return st;
+    DeviceGuard guard(ctx->device);
+    if (guard.status != QMC_OK) return guard.status;
+    hipStream_t hs = as_stream(stream);
+    const bool nus = nus_seeds != nullptr, shift = shifts != nullptr, sxor = (flags & QMC_SHIFT_XOR) != 0;
+    const bool fast = (first % 4 == 0) && (ld % 4 == 0) && aligned16(out_u32) && aligned16(out_f32);
+    const uint32_t q = log2_parts;
+    clear_launch_error();
+    with_bool(nus, [&](auto NUS) {
+        with_bool(shift, [&](auto SH) {
+            with_bool(sxor && shift, [&](auto SX) {
+                with_outputs(out_u32 != nullptr, out_f32 != nullptr, [&](auto WU, auto WF) {
+                    over_pieces(first, n, [&](uint64_t f, uint32_t nn, uint64_t off) {
+                        uint32_t* ou = out_u32 ? out_u32 + off : nullptr;
+                        float* of = out_f32 ? out_f32 + off : nullptr;
+                        if (fast) {
+                            with_bool(ctx->sobol_tune.nontemporal != 0, [&](auto NT) {
+                                uint32_t nchunks;
+                                const GenTune& tn = ctx->sobol_tune;
+                                const dim3 grid = fast_grid(nn, s, tn, &nchunks);
+                                hipLaunchKernelGGL(
+                                    (sobol64_fast<NUS.value, SH.value, SX.value, WU.value, WF.value, NT.value>), grid,
+                                    dim3(kWave), 0, hs, matrices, columns, q, r, f, nn, nus_seeds, shifts, ou, of, ld,
+                                    tn.chunks_per_wave, nchunks);
+                            });
+                        } else {
+                            hipLaunchKernelGGL((sobol64_general<NUS.value, SH.value, SX.value, WU.value, WF.value>),
+                                               dim3(general_grid(ctx, nn)), dim3(kBlock), 0, hs, matrices, columns, s,
+                                               q, r, f, nn, nus_seeds, shifts, ou, of, ld);
+                        }
+                    });
+                });
+            });
+        });
+    });
+    return check_launch(who);
+}
+
+extern "C" qmc_status qmc_generate_lattice64(qmc_context ctx, qmc_stream stream, const uint32_t* generator,
+                                             uint32_t s, uint32_t log2_parts, uint32_t part, uint64_t first,
+                                             uint64_t n, const uint32_t* shifts, uint32_t flags, uint32_t* out_u32,
+                                             float* out_f32, uint64_t ld) {
+    const char* who = "qmc_generate_lattice64";
+    uint32_t r = 0;
+    qmc_status st = validate_partition(who, 64, log2_parts, part, &r);
+    if (st != QMC_OK) return st;
+    st = validate_generation(who, ctx, generator, 4, s, first, n, flags, QMC_SHIFT_XOR | QMC_LATTICE_BACKWARD, shifts,
+                             nullptr, out_u32, out_f32, ld, 64 - log2_parts);
+    if (st != QMC_OK || n == 0) return st;
+    DeviceGuard guard(ctx->device);
+    if (guard.status != QMC_OK) return guard.status;
+    hipStream_t hs = as_stream(stream);
+    const bool back = (flags & QMC_LATTICE_BACKWARD) != 0, shift = shifts != nullptr;
+    const bool sxor = (flags & QMC_SHIFT_XOR) != 0;
+    const bool fast = (first % 4 == 0) && (ld % 4 == 0) && aligned16(out_u32) && aligned16(out_f32);
+    const uint32_t q = log2_parts;
+    clear_launch_error();
+    with_bool(back, [&](auto BK) {
+        with_bool(shift, [&](auto SH) {
+            with_bool(sxor && shift, [&](auto SX) {
+                with_outputs(out_u32 != nullptr, out_f32 != nullptr, [&](auto WU, auto WF) {
+                    over_pieces(first, n, [&](uint64_t f, uint32_t nn, uint64_t off) {
+                        uint32_t* ou = out_u32 ? out_u32 + off : nullptr;
+                        float* of = out_f32 ? out_f32 + off : nullptr;
+                        if (fast) {
+                            with_bool(ctx->lattice_tune.nontemporal != 0, [&](auto NT) {
+                                uint32_t nchunks;
+                                const GenTune& tn = ctx->lattice_tune;
+                                const dim3 grid = fast_grid(nn, s, tn, &nchunks);
+                                hipLaunchKernelGGL(
+                                    (lattice64_fast<BK.value, SH.value, SX.value, WU.value, WF.value, NT.value>), grid,
+                                    dim3(kWave), 0, hs, generator, q, r, f, nn, shifts, ou, of, ld,
+                                    tn.chunks_per_wave, nchunks);
+                            });
+                        } else {
+                            hipLaunchKernelGGL((lattice64_general<BK.value, SH.value, SX.value, WU.value, WF.value>),
+                                               dim3(general_grid(ctx, nn)), dim3(kBlock), 0, hs, generator, s, q, r,
+                                               f, nn, shifts, ou, of, ld);
+                        }
+                    });
                 });
             });
         });

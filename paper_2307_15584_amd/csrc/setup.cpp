@@ -81,6 +81,13 @@ extern "C" qmc_status qmc_primitive_polynomials(uint32_t count, uint32_t* codes)
 }
 
 extern "C" qmc_status qmc_sobol_matrices(uint32_t s, const uint32_t* direction_init, uint32_t* matrices) {
+    return qmc_sobol_matrices_wide(s, direction_init, 32, matrices);
+}
+
+// Column k of a K-column matrix: the top 32 digits of the fraction m_(k+1) 2^-(k+1), i.e.
+// m_(k+1) << (31 - k) below 32 and m_(k+1) >> (k - 31) from 32 on (m_(k+1) < 2^(k+1) <= 2^64).
+extern "C" qmc_status qmc_sobol_matrices_wide(uint32_t s, const uint32_t* direction_init, uint32_t columns,
+                                              uint32_t* matrices) {
     if (!direction_init || !matrices) {
         qmc::last_error_slot() = "qmc_sobol_matrices: NULL argument";
         return QMC_ERR_INVALID_ARGUMENT;
@@ -89,11 +96,16 @@ extern "C" qmc_status qmc_sobol_matrices(uint32_t s, const uint32_t* direction_i
         qmc::last_error_slot() = "qmc_sobol_matrices: s must be in [1, QMC_MAX_DIMS]";
         return QMC_ERR_OUT_OF_RANGE;
     }
+    if (columns == 0 || columns > 64) {
+        qmc::last_error_slot() = "qmc_sobol_matrices_wide: columns must be in [1, 64]";
+        return QMC_ERR_OUT_OF_RANGE;
+    }
+    const int K = static_cast<int>(columns);
     std::vector<uint32_t> polys(s > 1 ? s - 1 : 1);
     if (s > 1) qmc_primitive_polynomials(s - 1, polys.data());
 
-    // Dimension 0: identity, column k has only the 2^-(k+1) digit.
-    for (int k = 0; k < 32; ++k) matrices[k] = 1u << (31 - k);
+    // Dimension 0: identity, column k has only the 2^-(k+1) digit (none past 2^-32).
+    for (int k = 0; k < K; ++k) matrices[k] = k < 32 ? 1u << (31 - k) : 0u;
 
     for (uint32_t j = 1; j < s; ++j) {
         const uint32_t p = polys[j - 1];
@@ -103,7 +115,7 @@ extern "C" qmc_status qmc_sobol_matrices(uint32_t s, const uint32_t* direction_i
             qmc::last_error_slot() = "qmc_sobol_matrices: polynomial degree above QMC_MAX_DEGREE";
             return QMC_ERR_OUT_OF_RANGE;
         }
-        uint64_t m[32];
+        uint64_t m[64];
         const uint32_t* init = direction_init + size_t(j) * QMC_MAX_DEGREE;
         for (int k = 0; k < d; ++k) {
             m[k] = init[k];
@@ -114,13 +126,15 @@ extern "C" qmc_status qmc_sobol_matrices(uint32_t s, const uint32_t* direction_i
         }
         // Sobol' recurrence, in terms of the coefficient c_t of x^t (t = 1..d-1):
         //   m_k = m_(k-d) ^ (m_(k-d) << d) ^ XOR_t c_t (m_(k-d+t) << (d-t)).
-        for (int k = d; k < 32; ++k) {
+        for (int k = d; k < K; ++k) {
             uint64_t v = m[k - d] ^ (m[k - d] << d);
             for (int t = 1; t < d; ++t)
                 if ((p >> t) & 1u) v ^= m[k - d + t] << (d - t);
             m[k] = v;
         }
-        for (int k = 0; k < 32; ++k) matrices[j * 32 + k] = static_cast<uint32_t>((m[k] << (31 - k)) & 0xFFFFFFFFu);
+        for (int k = 0; k < K; ++k)
+            matrices[size_t(j) * K + k] =
+                static_cast<uint32_t>((k < 32 ? m[k] << (31 - k) : m[k] >> (k - 31)) & 0xFFFFFFFFu);
     }
     return QMC_OK;
 }
