@@ -554,6 +554,10 @@ __device__ __forceinline__ void for_each_task(const Args& a, F&& body) {
 // evaluated as exp2(-sum (c_j (x_j - u_j))^2) with c_j = a_j sqrt(log2 e), and the phase in
 // turns, phi = u_4 + sum_{j>=4} (a_j / 2 pi) x_j, reduced to [-1/2, 1/2] before the hardware
 // cosine (which takes its argument in turns).
+__device__ __forceinline__ float readlane_f(float v, uint32_t q) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
+}
+
 struct GenzPixel {
     float u[4], c[4], phi0, b[4];
     __device__ __forceinline__ void load(const Args& a, uint32_t p) {
@@ -567,6 +571,18 @@ struct GenzPixel {
             b[j] = pp[12 + j] * kInv2Pi;
         }
         phi0 = pp[4];
+    }
+    // The set held by lane q (wave-uniform result).
+    __device__ __forceinline__ GenzPixel from_lane(uint32_t q) const {
+        GenzPixel g;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            g.u[j] = readlane_f(u[j], q);
+            g.c[j] = readlane_f(c[j], q);
+            g.b[j] = readlane_f(b[j], q);
+        }
+        g.phi0 = readlane_f(phi0, q);
+        return g;
     }
     __device__ __forceinline__ float eval(const float (&x)[8]) const {
         float e = 0.0f;
@@ -598,15 +614,16 @@ __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
         const TileInfo ti = tile_info(a, task);
         float big_acc = 0.0f, small_acc = 0.0f;
         GenzPixel gbig;
-        // Each lane holds its own pixel's parameters when the tile has packed samples; a packed
-        // sample fetches its pixel's set from the owner lane.
+        // Each lane loads its own pixel's parameters once per tile, so the loads of all 64
+        // pixels are in flight together; a big pixel takes its set from the owner lane
+        // (wave-uniform), a packed sample through a lane shuffle.
         GenzPixel own;
-        if (ti.total && ti.inb && ti.ns) own.load(a, ti.p);
+        if (ti.inb && ti.n) own.load(a, ti.p);
         walk_tile<D, SK, NUS, SHIFT, BACK, false>(
             a, S, PX, task, ti.n, ti.inb, ti.off, ti.total,
             [&](uint32_t q) {
                 big_acc = 0.0f;
-                gbig.load(a, __builtin_amdgcn_readfirstlane(task * kTile + q));
+                gbig = own.from_lane(q);
             },
             [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t pp, bool is_big, uint32_t slot0, uint32_t) {
                 float f;
@@ -1093,14 +1110,20 @@ __global__ void reset_queue(uint32_t* q) { *q = 0u; }
 
 // ------------------------------------------------ materialised samples (plain) ----
 
-template <uint32_t SK, bool NUS, bool SHIFT, bool BACK>
+template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK>
 __global__ __launch_bounds__(kBlock) void pixel_samples(Args a) {
-    constexpr int D = QMC_MAX_DIMS;
     __shared__ SamplerLds<D> S;
     __shared__ PixelLds<D> PXs[kWavesPerBlock];
+    // per-pixel seeds of packed pixels in LDS (small dimension counts only)
+    constexpr bool kPacked = D <= 8;
+    __shared__ PackedSeeds<kPacked ? D : 1> PKs[kPacked ? kWavesPerBlock : 1];
     stage_sampler<D, SK, NUS>(S, a);
     __syncthreads();
     PixelLds<D>& PX = PXs[threadIdx.x >> 6];
+    PackedSeeds<D>* PK = nullptr;
+    if constexpr (kPacked) {
+        if (NUS || SHIFT || SK == QMC_SAMPLER_LATTICE) PK = &PKs[threadIdx.x >> 6];
+    }
     const uint32_t lane = lane_id();
     for_each_task(a, [&](uint32_t task) {
         const TileInfo ti = tile_info(a, task);
@@ -1115,7 +1138,7 @@ __global__ __launch_bounds__(kBlock) void pixel_samples(Args a) {
                         if (j0 + jj < a.d) a.out[uint64_t(j0 + jj) * a.out_ld + off] = x[jj];
                 }
             },
-            [&](uint32_t) {});
+            [&](uint32_t) {}, PK);
     });
 }
 
@@ -1301,11 +1324,12 @@ struct LobesStepFam {
     }
 };
 
+template <int D>
 struct SamplesFam {
     static constexpr bool kPoints = false;
     template <uint32_t SK, bool NUS, bool SH, bool BK>
     static void go(uint32_t grid, hipStream_t hs, const Args& a) {
-        hipLaunchKernelGGL((pixel_samples<SK, NUS, SH, BK>), dim3(grid), dim3(kBlock), 0, hs, a);
+        hipLaunchKernelGGL((pixel_samples<D, SK, NUS, SH, BK>), dim3(grid), dim3(kBlock), 0, hs, a);
     }
 };
 
@@ -1514,6 +1538,9 @@ extern "C" qmc_status qmc_generate_pixel_samples(qmc_context ctx, qmc_stream str
     const bool back = (sampler->flags & QMC_LATTICE_BACKWARD) != 0;
     clear_launch_error();
     if (a.dynamic) hipLaunchKernelGGL(reset_queue, dim3(1), dim3(1), 0, hs, a.queue);
-    dispatch_sampler<SamplesFam>(sampler->kind, nus, shift, back, grid, hs, a);
+    if (d <= 8)
+        dispatch_sampler<SamplesFam<8>>(sampler->kind, nus, shift, back, grid, hs, a);
+    else
+        dispatch_sampler<SamplesFam<QMC_MAX_DIMS>>(sampler->kind, nus, shift, back, grid, hs, a);
     return check_launch(who);
 }
