@@ -648,14 +648,59 @@ __device__ __forceinline__ uint32_t halton_value(uint32_t i, const HaltonBase& h
     return halton_component<MODE>(i, h, sig);
 }
 
-// Block (x, j): dimension j, chunks [x * cpw, min((x + 1) * cpw, nchunks)) of 256 indices, four
-// consecutive indices per lane (first % 4 == 0, ld % 4 == 0, 16-byte aligned outputs).
+// Per-dimension constants of the table-driven Halton kernel, computed on the host.  With
+// x = i mod b^M split as x = hi b^e + lo (lo: the e low digits), phi = R_e(lo) / b^e + H(hi) / b^M,
+// R_e the mirrored e-digit value and H the mirrored value of the M - e high digits (weights
+// b^(M-e-1) down to 1).  Both terms are kept as 64-bit fractions floor(2^64 .):
+//   flo[lo] = floor(2^64 R_e(lo) / b^e) = R_e(lo) qe + floor(R_e(lo) re / b^e),
+//   fhi(hi) = floor(2^64 H(hi) / b^M)   = H qm + floor(H rm / b^M),
+// with 2^64 = qe b^e + re = qm b^M + rm.  Their sum S satisfies S <= 2^64 phi < S + 2, so
+// floor(2^32 phi) is the high word of S unless its low word is 2^32 - 2 or 2^32 - 1 (then the
+// exact digit loop decides).  The table size b^e is chosen so that the high parts of a
+// wavefront's indices (`run` chunks of 256) span at most 64 consecutive values, one per lane:
+// b^e >= 17 for 4 chunks, b^e >= 34 for 8.
+struct HaltonDim {
+    uint64_t qm, qe;
+    uint32_t rm, re;
+    uint32_t e, le;      // low digits per table entry and b^e
+    uint32_t le_magic;   // ceil(2^32 / b^e): exact quotients of y < 2^32 / b^e
+    double inv_maxpow;   // 1 / b^M (estimate for floor(H rm / b^M))
+};
+struct HaltonTable {
+    HaltonDim d[QMC_MAX_DIMS];
+};
+
+constexpr uint32_t kHaltonMaxLow = 961;  // largest b^e (b = 31, e = 2, runs of 8 chunks)
+
+// Mirrored value of the `digits` low base-b digits of x (the lowest becomes the most significant).
+template <uint32_t MODE>
+__device__ __forceinline__ uint32_t mirrored_digits(uint32_t x, uint32_t digits, const HaltonBase& h,
+                                                    const uint32_t* sig) {
+    uint32_t r = 0;
+    for (uint32_t k = 0; k < digits; ++k) {
+        uint32_t qq = __umulhi(x, h.rcp);
+        uint32_t d = x - qq * h.b;
+        if (d >= h.b) {
+            ++qq;
+            d -= h.b;
+        }
+        r = r * h.b + (MODE == 0 ? d : sig[d]);
+        x = qq;
+    }
+    return r;
+}
+
+// Block (x, j): dimension j, chunks [x * run, (x + 1) * run) of 256 indices, four consecutive
+// indices per lane (first % 4 == 0, ld % 4 == 0, 16-byte aligned outputs); the table was made
+// for this run length.
 template <uint32_t MODE, bool WU, bool WF, bool NT>
 __global__ __launch_bounds__(kWave) void halton_fast(uint32_t first, uint32_t n, const uint32_t* __restrict__ factors,
                                                      uint32_t* __restrict__ ou, float* __restrict__ of, uint64_t ld,
-                                                     uint32_t cpw, uint32_t nchunks) {
+                                                     uint32_t run, uint32_t nchunks, HaltonTable tab) {
     dev::set_fp32_round_toward_zero();
     __shared__ uint32_t buf[2][kMaxBase + 1];
+    __shared__ uint64_t flo[kHaltonMaxLow];
+    __shared__ uint64_t fhi[kWave];
     const uint32_t j = blockIdx.y;
     HaltonBase h = halton_base(kPrimes[j]);
     const uint32_t f = MODE == 2 ? factors[j] : 1u;
@@ -663,18 +708,68 @@ __global__ __launch_bounds__(kWave) void halton_fast(uint32_t first, uint32_t n,
     const uint32_t* sig = nullptr;
     if constexpr (MODE != 0) sig = build_permutation<MODE>(h.b, f, buf);
     const uint32_t lane = threadIdx.x;
-    const uint32_t cb = blockIdx.x * cpw;
-    const uint32_t ce = min(cb + cpw, nchunks);
+    const uint32_t cb = blockIdx.x * run;
+    const uint32_t ce = min(cb + run, nchunks);
     const uint64_t base = uint64_t(j) * ld;
+    const uint32_t i0 = first + cb * kChunk;                 // first index of the wavefront
+    const uint32_t x0 = i0 % h.maxpow;                        // its reduced index
+    const uint32_t span = (ce - cb) * kChunk;
+    if (h.b == 2 || uint64_t(x0) + span > h.maxpow) {
+        // base 2, or the reduction wraps inside this wavefront's range: digit loop per index
+        for (uint32_t c = cb; c < ce; ++c) {
+            const uint32_t o = c * kChunk + 4u * lane;
+            const uint32_t i = first + o;
+            const uint32_t v0 = halton_value<MODE>(i, h, sig), v1 = halton_value<MODE>(i + 1u, h, sig);
+            const uint32_t v2 = halton_value<MODE>(i + 2u, h, sig), v3 = halton_value<MODE>(i + 3u, h, sig);
+            if (o + 4u <= n)
+                emit4<false, false, WU, WF, NT>(ou, of, base + o, 4u, v0, v1, v2, v3, 0u);
+            else if (o < n)
+                emit4<false, false, WU, WF, NT>(ou, of, base + o, n - o, v0, v1, v2, v3, 0u);
+        }
+        return;
+    }
+    const HaltonDim& hd = tab.d[j];
+    for (uint32_t t = lane; t < hd.le; t += kWave) {
+        const uint32_t r = mirrored_digits<MODE>(t, hd.e, h, sig);
+        flo[t] = uint64_t(r) * hd.qe + (r * hd.re) / hd.le;
+    }
+    // lane l: the high part hi = x0 / b^e + l
+    const uint32_t hw0 = x0 / hd.le;
+    {
+        const uint32_t H = mirrored_digits<MODE>(hw0 + lane, h.digits - hd.e, h, sig);
+        const uint64_t N = uint64_t(H) * hd.rm;
+        int64_t q = static_cast<int64_t>(static_cast<double>(N) * hd.inv_maxpow);
+        int64_t rem = static_cast<int64_t>(N - uint64_t(q) * h.maxpow);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            if (rem < 0) {
+                --q;
+                rem += h.maxpow;
+            } else if (rem >= int64_t(h.maxpow)) {
+                ++q;
+                rem -= h.maxpow;
+            }
+        }
+        fhi[lane] = uint64_t(H) * hd.qm + uint64_t(q);
+    }
+    __syncthreads();
+    const uint32_t y0 = x0 - hw0 * hd.le;  // offset of index i0 above hw0 b^e (below b^e)
     for (uint32_t c = cb; c < ce; ++c) {
         const uint32_t o = c * kChunk + 4u * lane;
-        const uint32_t i = first + o;
-        const uint32_t v0 = halton_value<MODE>(i, h, sig), v1 = halton_value<MODE>(i + 1u, h, sig);
-        const uint32_t v2 = halton_value<MODE>(i + 2u, h, sig), v3 = halton_value<MODE>(i + 3u, h, sig);
+        uint32_t v[4];
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) {
+            const uint32_t y = y0 + (o - cb * kChunk) + k;
+            const uint32_t dl = __umulhi(y, hd.le_magic);
+            const uint32_t lo = y - dl * hd.le;
+            const uint64_t S = flo[lo] + fhi[dl];
+            v[k] = static_cast<uint32_t>(S >> 32);
+            if (static_cast<uint32_t>(S) >= 0xFFFFFFFEu) v[k] = halton_component<MODE>(first + o + k, h, sig);
+        }
         if (o + 4u <= n)
-            emit4<false, false, WU, WF, NT>(ou, of, base + o, 4u, v0, v1, v2, v3, 0u);
+            emit4<false, false, WU, WF, NT>(ou, of, base + o, 4u, v[0], v[1], v[2], v[3], 0u);
         else if (o < n)
-            emit4<false, false, WU, WF, NT>(ou, of, base + o, n - o, v0, v1, v2, v3, 0u);
+            emit4<false, false, WU, WF, NT>(ou, of, base + o, n - o, v[0], v[1], v[2], v[3], 0u);
     }
 }
 
@@ -741,7 +836,6 @@ bool ranges_overlap(const void* a, uint64_t abytes, const void* b, uint64_t bbyt
     return a0 < b0 + bbytes && b0 < a0 + abytes;
 }
 
-// Shared validation of the generation calls.
 // first + n <= 2^bits (bits <= 64).
 bool index_range_ok(uint64_t first, uint64_t n, uint32_t bits) {
     if (bits >= 64) return n == 0 || n - 1 <= ~first;
@@ -749,6 +843,7 @@ bool index_range_ok(uint64_t first, uint64_t n, uint32_t bits) {
     return first <= lim && n <= lim - first;
 }
 
+// Shared validation of the generation calls.
 qmc_status validate_generation(const char* who, qmc_context ctx, const void* table, uint64_t table_bytes_per_dim,
                                uint32_t s, uint64_t first, uint64_t n, uint32_t flags, uint32_t allowed_flags,
                                const void* aux0, const void* aux1, const uint32_t* ou, const float* of, uint64_t ld,
@@ -779,6 +874,36 @@ qmc_status validate_generation(const char* who, qmc_context ctx, const void* tab
         if (ranges_overlap(ins[k], in_bytes[k], ou, out_bytes) || ranges_overlap(ins[k], in_bytes[k], of, out_bytes))
             return fail(QMC_ERR_INVALID_ARGUMENT, "%s: an output overlaps an input", who);
     return QMC_OK;
+}
+
+// Constants of halton_fast for the first s primes and runs of `run` chunks (see HaltonDim).
+void halton_table(uint32_t s, uint32_t run, HaltonTable* t) {
+    const uint64_t min_le = (uint64_t(kChunk) * run - 1) / 62 + 1;  // high parts span <= 64 values
+    static const uint32_t primes[QMC_MAX_DIMS] = {
+        2,   3,   5,   7,   11,  13,  17,  19,  23,  29,  31,  37,  41,  43,  47,  53,  59,  61,  67,  71,  73,  79,
+        83,  89,  97,  101, 103, 107, 109, 113, 127, 131, 137, 139, 149, 151, 157, 163, 167, 173, 179, 181, 191, 193,
+        197, 199, 211, 223, 227, 229, 233, 239, 241, 251, 257, 263, 269, 271, 277, 281, 283, 293, 307, 311};
+    const unsigned __int128 two64 = static_cast<unsigned __int128>(1) << 64;
+    for (uint32_t j = 0; j < s; ++j) {
+        const uint64_t b = primes[j];
+        uint64_t maxpow = b;
+        while (maxpow * b <= 0xFFFFFFFFull) maxpow *= b;
+        uint32_t e = 1;
+        uint64_t le = b;
+        while (le < min_le) {
+            le *= b;
+            ++e;
+        }
+        HaltonDim& d = t->d[j];
+        d.qm = static_cast<uint64_t>(two64 / maxpow);
+        d.rm = static_cast<uint32_t>(two64 % maxpow);
+        d.qe = static_cast<uint64_t>(two64 / le);
+        d.re = static_cast<uint32_t>(two64 % le);
+        d.e = e;
+        d.le = static_cast<uint32_t>(le);
+        d.le_magic = static_cast<uint32_t>(((uint64_t(1) << 32) + le - 1) / le);
+        d.inv_maxpow = 1.0 / static_cast<double>(maxpow);
+    }
 }
 
 // Grid of the fast kernels: x = runs of cpw chunks, y = dimension (dimension-major dispatch).
@@ -1063,15 +1188,18 @@ extern "C" qmc_status qmc_generate_halton(qmc_context ctx, qmc_stream stream, ui
     const bool fast = (first % 4 == 0) && (ld % 4 == 0) && aligned16(out_u32) && aligned16(out_f32);
     const uint32_t first32 = static_cast<uint32_t>(first);
     const uint32_t nn = static_cast<uint32_t>(n);
+    // digit tables cost more to set up with permutations: longer runs amortise them
+    const uint32_t run = mode == QMC_HALTON_IDENTITY ? 4u : 8u;
+    HaltonTable tab{};
+    if (fast) halton_table(s, run, &tab);
     clear_launch_error();
     auto launch = [&](auto MODE) {
         with_outputs(out_u32 != nullptr, out_f32 != nullptr, [&](auto WU, auto WF) {
             if (fast) {
                 const uint32_t nchunks = static_cast<uint32_t>((n + kChunk - 1) / kChunk);
-                const uint32_t cpw = 4;  // per-wavefront permutation set-up amortised over 1024 indices
                 hipLaunchKernelGGL((halton_fast<decltype(MODE)::value, WU.value, WF.value, false>),
-                                   dim3((nchunks + cpw - 1) / cpw, s), dim3(kWave), 0, hs, first32, nn, factors,
-                                   out_u32, out_f32, ld, cpw, nchunks);
+                                   dim3((nchunks + run - 1) / run, s), dim3(kWave), 0, hs, first32, nn, factors,
+                                   out_u32, out_f32, ld, run, nchunks, tab);
             } else {
                 const uint64_t want = (n + kWave - 1) / kWave;
                 const uint32_t gx = static_cast<uint32_t>(std::min<uint64_t>(want, uint64_t(ctx->num_cus) * 16));

@@ -84,6 +84,41 @@ def test_halton_first_b_power_points_stratify_at_scale(qmc):
         assert np.array_equal(got, want), (b, m)
 
 
+def _just_below_a_grid_point(b, sig):
+    """The index x < b^M whose value lies closest below a multiple of 2^-32: its mirrored digit
+    value R has 2^32 R = -1 mod b^M.  There the table-driven kernel's 64-bit fixed-point sum
+    cannot decide the last bit for some bases and the exact digit loop takes over."""
+    bm = halton.max_power(b)
+    digits = 0
+    while b ** (digits + 1) <= bm:
+        digits += 1
+    r = (-pow(1 << 32, -1, bm)) % bm
+    inv = {v: a for a, v in enumerate(sig)}
+    x = 0
+    for p in range(digits):          # digit p of R (lowest first) is sigma(a_(digits-1-p))
+        r, d = divmod(r, b)
+        x += inv[d] * b ** (digits - 1 - p)
+    return x
+
+
+@pytest.mark.parametrize("mode", ["identity", "faure"])
+def test_halton_near_grid_points_every_base(qmc, mode):
+    import torch
+
+    bases = halton.primes(64)
+    for j in range(1, 64):
+        b = bases[j]
+        sig = halton.digit_permutation(b, mode)
+        x = _just_below_a_grid_point(b, sig)
+        first = max(0, (x & ~3) - 128)
+        n = 256
+        u, _ = qmc.qmc_generate_halton(j + 1, first, n, MODES[mode], None, want_f32=False)
+        torch.cuda.synchronize()
+        got = qmc.to_u32(u)[j, :n]
+        want = [halton.radical_inverse_u32(first + t, b, sig) for t in range(n)]
+        assert [int(v) for v in got] == want, (b, x)
+
+
 def test_halton_argument_errors(qmc):
     with pytest.raises(qmc.QMCError) as e:
         qmc.qmc_generate_halton(4, 0, 100, 3)
