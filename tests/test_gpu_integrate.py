@@ -97,6 +97,8 @@ LOBE_CASES = [
     (5, 70, "edge", 21, 4, "sobol", NUS | SHIFT),          # d < 8, more lobes than one group
     (64, 32, "64", 8, 4, "sobol", NUS | SHIFT),            # two 32-dim halves per lobe
     (20, 7, "edge", 9, 3, "lattice", SHIFT | BACK),
+    (50, 45, "edge", 7, 5, "sobol", NUS | SHIFT),          # d > 32: quarters of 16 dims, two lobe groups
+    (40, 33, "64", 5, 3, "lattice", SHIFT),                # one lobe in the second group
 ]
 
 
