@@ -439,59 +439,98 @@ __global__ __launch_bounds__(kBlock) void lattice64_general(const uint32_t* __re
 
 // ------------------------------------------------------------ point-major ----
 //
-// out[(i - first) * ld + j]: a wavefront takes 64 consecutive points, forms the s components
-// of its lane's point one dimension at a time into an LDS tile, then writes the tile row by
-// row, so every store covers one point's s consecutive words.
+// out[(i - first) * ld + j]: a wavefront takes 64 consecutive points, forms up to 32
+// components of its lane's point into an LDS tile, then writes the tile row by row (two rows
+// of 128 bytes per store instruction), and repeats for the next 32 dimensions.  Blocks of four
+// wavefronts share the staged matrices, so the LDS a wavefront needs stays small and more of
+// them stream at once.
+
+constexpr uint32_t kPmWaves = 4;  // wavefronts per block
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // The point of index i = 64 h + lane (first a multiple of 64) is the XOR of a part from the
 // high index bits, the same for the whole wavefront (lanes 6..31 select a column each, XOR
-// reduction in DPP), and a part from the lane's six low bits; other starts use the plain
-// matrix product.
-template <bool NUS, bool SHIFT, bool SXOR, bool WU, bool WF, bool SPLIT>
-__global__ __launch_bounds__(kWave) void sobol_point_major(const uint32_t* __restrict__ mats, uint32_t s,
-                                                           uint32_t first, uint32_t n,
-                                                           const uint32_t* __restrict__ seeds,
-                                                           const uint32_t* __restrict__ shifts,
-                                                           uint32_t* __restrict__ ou, float* __restrict__ of,
-                                                           uint64_t ld) {
+// reduction in DPP), and a part from the lane's six low bits, tabulated per dimension and lane
+// once per block; other starts use the plain matrix product.  SM: dimensions the block stages
+// (32 or 64).
+template <int SM, bool NUS, bool SHIFT, bool SXOR, bool WU, bool WF, bool SPLIT>
+__global__ __launch_bounds__(kWave * kPmWaves) void sobol_point_major(const uint32_t* __restrict__ mats, uint32_t s,
+                                                                      uint32_t first, uint32_t n,
+                                                                      const uint32_t* __restrict__ seeds,
+                                                                      const uint32_t* __restrict__ shifts,
+                                                                      uint32_t* __restrict__ ou, float* __restrict__ of,
+                                                                      uint64_t ld) {
     dev::set_fp32_round_toward_zero();
-    __shared__ SobolLds L;
-    __shared__ uint32_t tile[kWave][QMC_MAX_DIMS + 1];
-    stage_sobol<NUS, SHIFT>(L, mats, s, seeds, shifts);
-    const uint32_t lane = threadIdx.x;
+    __shared__ uint32_t cols[SM][32];
+    __shared__ uint32_t seed[SM], smul[SM], shift[SM];
+    __shared__ uint32_t lo[SPLIT ? SM : 1][kWave];
+    __shared__ uint32_t tiles[kPmWaves][kWave][33];
+    for (uint32_t t = threadIdx.x; t < s * 32; t += blockDim.x) {
+        const uint32_t c = mats[t];
+        cols[t >> 5][t & 31] = NUS ? dev::brev(c) : c;
+    }
+    for (uint32_t t = threadIdx.x; t < s; t += blockDim.x) {
+        if constexpr (NUS) {
+            seed[t] = seeds[t];
+            smul[t] = dev::seed_multiplier(seeds[t]);
+        }
+        if constexpr (SHIFT) shift[t] = shifts[t];
+    }
+    __syncthreads();
+    if constexpr (SPLIT) {
+        for (uint32_t t = threadIdx.x; t < s * kWave; t += blockDim.x) {
+            const uint32_t j = t / kWave, l = t % kWave;
+            uint32_t x = 0;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) x ^= (0u - ((l >> k) & 1u)) & cols[j][k];
+            lo[j][l] = x;
+        }
+        __syncthreads();
+    }
+    const uint32_t wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const uint32_t k32 = lane & 31u;
-    for (uint32_t o0 = blockIdx.x * kWave; o0 < n; o0 += gridDim.x * kWave) {
+    uint32_t(&tile)[kWave][33] = tiles[wave];
+    // wavefronts run different numbers of tiles: only wavefront-level synchronisation below
+    for (uint32_t o0 = (blockIdx.x * kPmWaves + wave) * kWave; o0 < n; o0 += gridDim.x * kPmWaves * kWave) {
         const uint32_t i = first + o0 + lane;
         const uint32_t h = (first + o0) >> 6;
-        for (uint32_t j = 0; j < s; ++j) {
-            uint32_t v;
-            if constexpr (SPLIT) {
-                const uint32_t part = half_wave_xor((k32 >= 6u && ((h >> (k32 - 6u)) & 1u)) ? L.cols[j][k32] : 0u);
-                v = __builtin_amdgcn_readlane(part, 31);
-#pragma unroll
-                for (int k = 0; k < 6; ++k) v ^= (0u - ((lane >> k) & 1u)) & L.cols[j][k];
-            } else {
-                v = matrix_product(L.cols[j], i);
-            }
-            if constexpr (NUS) v = dev::nus_from_mirrored(v, L.seed[j], L.sm[j]);
-            if constexpr (SHIFT) v = dev::apply_shift<SXOR>(v, L.shift[j]);
-            tile[lane][j] = v;
-        }
-        __syncthreads();
         const uint32_t rows = min(n - o0, kWave);
-        // two rows per store instruction when a row fits half a wavefront
-        const uint32_t per = s <= 32 ? 2u : 1u;
-        const uint32_t sub = s <= 32 ? (lane >> 5) : 0u, col = s <= 32 ? k32 : lane;
-        for (uint32_t r0 = 0; r0 < rows; r0 += per) {
-            const uint32_t r = r0 + sub;
-            if (col < s && r < rows) {
-                const uint32_t v = tile[r][col];
-                const uint64_t at = uint64_t(o0 + r) * ld + col;
-                if constexpr (WU) ou[at] = v;
-                if constexpr (WF) of[at] = dev::u32_to_unifloat_rtz(v);
+        for (uint32_t j0 = 0; j0 < s; j0 += 32) {
+            const uint32_t sg = min(s - j0, 32u);
+#pragma unroll 4
+            for (uint32_t jj = 0; jj < sg; ++jj) {
+                const uint32_t j = j0 + jj;
+                uint32_t v;
+                if constexpr (SPLIT) {
+                    const uint32_t part = half_wave_xor((k32 >= 6u && ((h >> (k32 - 6u)) & 1u)) ? cols[j][k32] : 0u);
+                    v = __builtin_amdgcn_readlane(part, 31) ^ lo[j][lane];
+                } else {
+                    v = matrix_product(cols[j], i);
+                }
+                if constexpr (NUS) v = dev::nus_from_mirrored(v, seed[j], smul[j]);
+                if constexpr (SHIFT) v = dev::apply_shift<SXOR>(v, shift[j]);
+                tile[lane][jj] = v;
             }
+            wave_sync();
+            // two rows (points) per store instruction
+            const uint32_t sub = lane >> 5;
+#pragma unroll 4
+            for (uint32_t r0 = 0; r0 < rows; r0 += 2) {
+                const uint32_t r = r0 + sub;
+                if (k32 < sg && r < rows) {
+                    const uint32_t v = tile[r][k32];
+                    const uint64_t at = uint64_t(o0 + r) * ld + j0 + k32;
+                    if constexpr (WU) ou[at] = v;
+                    if constexpr (WF) of[at] = dev::u32_to_unifloat_rtz(v);
+                }
+            }
+            wave_sync();
         }
-        __syncthreads();
     }
 }
 
@@ -953,13 +992,19 @@ extern "C" qmc_status qmc_generate_sobol(qmc_context ctx, qmc_stream stream, con
             with_bool(sxor && shift, [&](auto SX) {
                 with_outputs(out_u32 != nullptr, out_f32 != nullptr, [&](auto WU, auto WF) {
                     if (pm) {
-                        const uint64_t want = (n + kWave - 1) / kWave;
-                        const uint32_t gx = static_cast<uint32_t>(std::min<uint64_t>(want, uint64_t(ctx->num_cus) * 32));
+                        const uint64_t want = (n + kWave * kPmWaves - 1) / (kWave * kPmWaves);
+                        const uint32_t gx = static_cast<uint32_t>(std::min<uint64_t>(want, uint64_t(ctx->num_cus) * 8));
                         with_bool(first % kWave == 0, [&](auto SPLIT) {
-                            hipLaunchKernelGGL(
-                                (sobol_point_major<NUS.value, SH.value, SX.value, WU.value, WF.value, SPLIT.value>),
-                                dim3(gx), dim3(kWave), 0, hs, matrices, s, first32, nn, nus_seeds, shifts, out_u32,
-                                out_f32, ld);
+                            auto go = [&](auto SMV) {
+                                hipLaunchKernelGGL((sobol_point_major<decltype(SMV)::value, NUS.value, SH.value, SX.value,
+                                                                     WU.value, WF.value, SPLIT.value>),
+                                                   dim3(gx), dim3(kWave * kPmWaves), 0, hs, matrices, s, first32, nn,
+                                                   nus_seeds, shifts, out_u32, out_f32, ld);
+                            };
+                            if (s <= 32)
+                                go(std::integral_constant<int, 32>{});
+                            else
+                                go(std::integral_constant<int, QMC_MAX_DIMS>{});
                         });
                     } else if (fast) {
                         with_bool(ctx->sobol_tune.nontemporal != 0, [&](auto NT) {

@@ -263,3 +263,21 @@ def test_point_major_layout(qmc, kind, s, first, n, flags, ld):
     assert np.array_equal(gf[:, :s], ef.view(np.uint32).T)
     if ldv > s:
         assert (gu[:, s:] == 7).all() and (out_f[:, s:] == 2.0).all().item()
+
+
+def test_point_major_many_tiles_per_wavefront(qmc):
+    """More 64-point tiles than wavefronts (each wavefront loops over several, unevenly) with two
+    groups of dimensions (s = 33): 3000 sampled points against the oracle, whole rows."""
+    import torch
+
+    s, first, n = 33, 64 * 7, (1 << 21) + 37
+    m = _mats(s)
+    seeds, shifts = nus_seeds(s, 1), cp_shifts(s, 2)
+    out_u = torch.empty((n, s), dtype=torch.int32, device="cuda")
+    qmc.qmc_generate_sobol(qmc.from_u32(m), first, n, qmc.from_u32(seeds), qmc.from_u32(shifts),
+                           qmc.QMC_POINT_MAJOR, out_u32=out_u, ld=s)
+    rows = np.sort(np.random.default_rng(12).choice(n, 3000, replace=False))
+    rows[-1] = n - 1
+    got = qmc.to_u32(out_u[torch.from_numpy(rows).cuda()])
+    want = generate.sobol_at(m, first + rows.astype(np.uint64), seeds, shifts, 0)
+    assert np.array_equal(got, want.T)
