@@ -520,6 +520,11 @@ def main():
     out["sobol_point_major_2p24x32"] = {"kernel_ms": round(pm_ms, 4),
                                         "gpts_dim_per_s": round(s * n / (pm_ms * 1e-3) / 1e9, 1),
                                         "hbm_frac": round(alg_bytes / (pm_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    lpm_ms = _event_ms(torch, lambda: q.qmc_generate_lattice(gvec, 0, n, shifts, q.QMC_POINT_MAJOR, out_u32=pm_u,
+                                                              out_f32=pm_f, ld=s), 5)
+    out["lattice_point_major_2p24x32"] = {"kernel_ms": round(lpm_ms, 4),
+                                          "gpts_dim_per_s": round(s * n / (lpm_ms * 1e-3) / 1e9, 1),
+                                          "hbm_frac": round(alg_bytes / (lpm_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     # 64-bit indices and partitioned enumeration: part 77 of 2^8 from m = 2^44 (global indices
     # near 2^52), the same 2^24 x 32 scrambled + rotated workload as the headline kernel
     wide = q.from_u32(q.qmc_sobol_matrices_wide(s, sobol_direction_init(s, 0), 64))

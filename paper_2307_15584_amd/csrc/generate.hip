@@ -534,27 +534,47 @@ __global__ __launch_bounds__(kWave * kPmWaves) void sobol_point_major(const uint
     }
 }
 
+// Lattice points in the same tiles: a lane forms brev(i) once and multiplies it by each
+// component of the generator (Alg. 4).
 template <bool BACK, bool SHIFT, bool SXOR, bool WU, bool WF>
-__global__ __launch_bounds__(kWave) void lattice_point_major(const uint32_t* __restrict__ gen, uint32_t s,
-                                                             uint32_t first, uint32_t n,
-                                                             const uint32_t* __restrict__ shifts,
-                                                             uint32_t* __restrict__ ou, float* __restrict__ of,
-                                                             uint64_t ld) {
+__global__ __launch_bounds__(kWave * kPmWaves) void lattice_point_major(const uint32_t* __restrict__ gen, uint32_t s,
+                                                                        uint32_t first, uint32_t n,
+                                                                        const uint32_t* __restrict__ shifts,
+                                                                        uint32_t* __restrict__ ou,
+                                                                        float* __restrict__ of, uint64_t ld) {
     dev::set_fp32_round_toward_zero();
     __shared__ LatticeLds L;
+    __shared__ uint32_t tiles[kPmWaves][kWave][33];
     stage_lattice<SHIFT>(L, gen, s, shifts);
-    const uint32_t lane = threadIdx.x;
-    // lane l writes component l of each point: the stores of one point are s consecutive words
-    if (lane >= s) return;
-    const uint32_t g = L.g[lane];
-    const uint32_t sh = SHIFT ? L.shift[lane] : 0u;
-    for (uint32_t o = blockIdx.x * kWave; o < min(n, blockIdx.x * kWave + kWave); ++o) {
-        const uint32_t i = first + o;
-        uint32_t v = dev::brev(BACK ? ~i : i) * g;
-        if constexpr (SHIFT) v = dev::apply_shift<SXOR>(v, sh);
-        const uint64_t at = uint64_t(o) * ld + lane;
-        if constexpr (WU) ou[at] = v;
-        if constexpr (WF) of[at] = dev::u32_to_unifloat_rtz(v);
+    const uint32_t wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const uint32_t k32 = lane & 31u;
+    uint32_t(&tile)[kWave][33] = tiles[wave];
+    for (uint32_t o0 = (blockIdx.x * kPmWaves + wave) * kWave; o0 < n; o0 += gridDim.x * kPmWaves * kWave) {
+        const uint32_t i = first + o0 + lane;
+        const uint32_t b = dev::brev(BACK ? ~i : i);
+        const uint32_t rows = min(n - o0, kWave);
+        for (uint32_t j0 = 0; j0 < s; j0 += 32) {
+            const uint32_t sg = min(s - j0, 32u);
+#pragma unroll 4
+            for (uint32_t jj = 0; jj < sg; ++jj) {
+                uint32_t v = b * L.g[j0 + jj];
+                if constexpr (SHIFT) v = dev::apply_shift<SXOR>(v, L.shift[j0 + jj]);
+                tile[lane][jj] = v;
+            }
+            wave_sync();
+            const uint32_t sub = lane >> 5;
+#pragma unroll 4
+            for (uint32_t r0 = 0; r0 < rows; r0 += 2) {
+                const uint32_t r = r0 + sub;
+                if (k32 < sg && r < rows) {
+                    const uint32_t v = tile[r][k32];
+                    const uint64_t at = uint64_t(o0 + r) * ld + j0 + k32;
+                    if constexpr (WU) ou[at] = v;
+                    if constexpr (WF) of[at] = dev::u32_to_unifloat_rtz(v);
+                }
+            }
+            wave_sync();
+        }
     }
 }
 
@@ -1057,9 +1077,11 @@ extern "C" qmc_status qmc_generate_lattice(qmc_context ctx, qmc_stream stream, c
             with_bool(sxor && shift, [&](auto SX) {
                 with_outputs(out_u32 != nullptr, out_f32 != nullptr, [&](auto WU, auto WF) {
                     if (pm) {
+                        const uint64_t want = (n + kWave * kPmWaves - 1) / (kWave * kPmWaves);
+                        const uint32_t gx = static_cast<uint32_t>(std::min<uint64_t>(want, uint64_t(ctx->num_cus) * 8));
                         hipLaunchKernelGGL((lattice_point_major<BK.value, SH.value, SX.value, WU.value, WF.value>),
-                                           dim3(static_cast<uint32_t>((n + kWave - 1) / kWave)), dim3(kWave), 0, hs,
-                                           generator, s, first32, nn, shifts, out_u32, out_f32, ld);
+                                           dim3(gx), dim3(kWave * kPmWaves), 0, hs, generator, s, first32, nn, shifts,
+                                           out_u32, out_f32, ld);
                     } else if (fast) {
                         with_bool(ctx->lattice_tune.nontemporal != 0, [&](auto NT) {
                             uint32_t nchunks;

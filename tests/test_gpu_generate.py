@@ -236,6 +236,7 @@ def test_autotune_generate_reports_candidates(qmc):
     ("sobol", 3, (1 << 32) - 64 * 40, 64 * 40, 0, None),
     ("lattice", 32, 0, 5000, BACK, None),
     ("lattice", 5, 13, 777, XOR, 8),
+    ("lattice", 40, 64 * 3, 3000, XOR, 41),     # two groups of dimensions
 ])
 def test_point_major_layout(qmc, kind, s, first, n, flags, ld):
     """out[(i - first) * ld + j] against the oracle, bit for bit, and nothing written between
@@ -267,7 +268,8 @@ def test_point_major_layout(qmc, kind, s, first, n, flags, ld):
 
 def test_point_major_many_tiles_per_wavefront(qmc):
     """More 64-point tiles than wavefronts (each wavefront loops over several, unevenly) with two
-    groups of dimensions (s = 33): 3000 sampled points against the oracle, whole rows."""
+    groups of dimensions (s = 33): 3000 sampled points against the oracle, whole rows, for the
+    Sobol' and the lattice generator."""
     import torch
 
     s, first, n = 33, 64 * 7, (1 << 21) + 37
@@ -280,4 +282,10 @@ def test_point_major_many_tiles_per_wavefront(qmc):
     rows[-1] = n - 1
     got = qmc.to_u32(out_u[torch.from_numpy(rows).cuda()])
     want = generate.sobol_at(m, first + rows.astype(np.uint64), seeds, shifts, 0)
+    assert np.array_equal(got, want.T)
+    g = lattice_vector(s, 20, 3)
+    qmc.qmc_generate_lattice(qmc.from_u32(g), first, n, qmc.from_u32(shifts), qmc.QMC_POINT_MAJOR | BACK,
+                             out_u32=out_u, ld=s)
+    got = qmc.to_u32(out_u[torch.from_numpy(rows).cuda()])
+    want = generate.lattice_at(g, first + rows.astype(np.uint64), shifts, BACK)
     assert np.array_equal(got, want.T)
