@@ -408,6 +408,12 @@ __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S,
     const uint32_t row = RS == kWave ? lane : lane % RS;
     const uint32_t j0 = gen_first_dim<D>();
     const uint32_t p0 = task * kTile;
+    // Hilbert-shifted lattice: each lane forms its own pixel's shift once per tile, for the big
+    // pixels (read from the owner lane) and the packed ones alike
+    uint32_t hs_own = 0;
+    if constexpr (SK == QMC_SAMPLER_LATTICE) {
+        if (a.lhilbert && p0 + lane < a.num_pixels) hs_own = pixel_hilbert_shift(a, p0 + lane);
+    }
     uint64_t bigmask = __ballot(inb && n >= kWave);
     while (bigmask) {
         const uint32_t q = __builtin_ctzll(bigmask);
@@ -431,7 +437,7 @@ __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S,
             }
         }
         if constexpr (SK == QMC_SAMPLER_LATTICE) {
-            if (a.lhilbert && lane == 0) PX.hshift = pixel_hilbert_shift(a, pp);
+            if (a.lhilbert && lane == 0) PX.hshift = __builtin_amdgcn_readlane(hs_own, q);
         }
         wave_sync();
         on_big_begin(q);
@@ -480,7 +486,7 @@ __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S,
             if constexpr (SHIFT) PK->shift[j][lane] = dev::pcg_hash(S.kc[j] ^ (p0 + lane));
         }
         if constexpr (SK == QMC_SAMPLER_LATTICE) {
-            if (a.lhilbert && p0 + lane < a.num_pixels) PK->hshift[lane] = pixel_hilbert_shift(a, p0 + lane);
+            if (a.lhilbert) PK->hshift[lane] = hs_own;
         }
         wave_sync();
     }
