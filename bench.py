@@ -140,6 +140,19 @@ def cpu_pixel_oracle():
     dt = time.perf_counter() - t0
     out["lobes_fwd_bwd"] = {"pixel_samples_per_s": round(len(px) * 64 / dt, 1), "cores": 1,
                             "crop": "12x12 pixels x 64 spp (estimate, L2 loss and analytic gradient)"}
+    # one 64-spp pass of the 3840x2160 progressive run (d = 64, 32 lobes)
+    W5, H5 = 3840, 2160
+    m64 = digital.sobol_matrices(64, sobol_direction_init(64, 0))
+    sp5 = {"kind": "sobol", "s": 64, "table": m64, "seed": 0xC5,
+           "flags": estimator.PIXEL_NUS | estimator.PIXEL_SHIFT}
+    c5 = counts_uniform(W5, H5, 64)
+    ig5 = {"kind": "lobes", "d": 64, "num_lobes": 32, "params": lobe_params(32, 64, 6), "pixel_seed": 9}
+    px = (np.arange(16)[:, None] * W5 + np.arange(16)[None, :]).ravel()
+    t0 = time.perf_counter()
+    estimator.integrate_pixels(sp5, ig5, c5, px)
+    dt = time.perf_counter() - t0
+    out["progressive_d64_fwd"] = {"pixel_samples_per_s": round(len(px) * 64 / dt, 1), "cores": 1,
+                                  "crop": "16x16 pixels x 64 spp of the 3840x2160 run (one pass)"}
     return out
 
 
