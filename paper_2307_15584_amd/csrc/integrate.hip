@@ -533,14 +533,18 @@ __device__ __forceinline__ TileInfo tile_info(const Args& a, uint32_t task) {
     return t;
 }
 
-__device__ __forceinline__ void write_pixel(const Args& a, uint32_t p, float window_sum) {
-    const uint32_t N = a.counts[p];
+// Stores the pixel's running sum and mean given its total count N.
+__device__ __forceinline__ void write_pixel_n(const Args& a, uint32_t p, float window_sum, uint32_t N) {
     float total = window_sum;
     if (a.sums) {
         total = a.sums[p] + window_sum;
         a.sums[p] = total;
     }
     if (a.means) a.means[p] = N ? total / static_cast<float>(N) : 0.0f;
+}
+
+__device__ __forceinline__ void write_pixel(const Args& a, uint32_t p, float window_sum) {
+    write_pixel_n(a, p, window_sum, a.counts[p]);
 }
 
 // Runs body(task) for every task this wavefront obtains.
@@ -625,6 +629,7 @@ __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
         // (wave-uniform), a packed sample through a lane shuffle.
         GenzPixel own;
         if (ti.inb && ti.n) own.load(a, ti.p);
+        const uint32_t n_own = ti.inb ? a.counts[ti.p] : 0u;  // a big pixel's count, from its lane
         walk_tile<D, SK, NUS, SHIFT, BACK, false>(
             a, S, PX, task, ti.n, ti.inb, ti.off, ti.total,
             [&](uint32_t q) {
@@ -660,10 +665,11 @@ __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
             },
             [&](uint32_t q) {
                 const float t = wave_sum(big_acc);
-                if (lane == 0) write_pixel(a, task * kTile + q, t);
+                const uint32_t nq = __builtin_amdgcn_readlane(n_own, q);
+                if (lane == 0) write_pixel_n(a, task * kTile + q, t, nq);
             },
             PK);
-        if (ti.inb && ti.n < kWave) write_pixel(a, ti.p, small_acc);
+        if (ti.inb && ti.n < kWave) write_pixel_n(a, ti.p, small_acc, n_own);
     });
 }
 
