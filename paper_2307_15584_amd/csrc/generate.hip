@@ -618,53 +618,77 @@ __device__ __forceinline__ HaltonBase halton_base(uint32_t b) {
     return h;
 }
 
-// Size of the table after `steps` reductions of Faure's recursion from b (b -> b/2 if even,
-// b -> b-1 if odd).
-__device__ __forceinline__ uint32_t faure_chain(uint32_t b, uint32_t steps) {
-    for (uint32_t k = 0; k < steps; ++k) b = (b & 1u) ? b - 1u : b >> 1;
-    return b;
+// Faure's permutations of the first QMC_MAX_DIMS primes, one after another, formed at compile
+// time: sigma_2 = (0, 1); for even y, 2 sigma_{y/2} followed by 2 sigma_{y/2} + 1; for odd y,
+// sigma_{y-1} with every value >= (y-1)/2 raised by one and (y-1)/2 inserted in the middle.
+constexpr uint32_t kPrimeList[QMC_MAX_DIMS] = {
+    2,   3,   5,   7,   11,  13,  17,  19,  23,  29,  31,  37,  41,  43,  47,  53,  59,  61,  67,  71,  73,  79,
+    83,  89,  97,  101, 103, 107, 109, 113, 127, 131, 137, 139, 149, 151, 157, 163, 167, 173, 179, 181, 191, 193,
+    197, 199, 211, 223, 227, 229, 233, 239, 241, 251, 257, 263, 269, 271, 277, 281, 283, 293, 307, 311};
+
+constexpr uint32_t faure_total() {
+    uint32_t t = 0;
+    for (uint32_t j = 0; j < QMC_MAX_DIMS; ++j) t += kPrimeList[j];
+    return t;
 }
 
-// Digit permutation of base b into sig (one wavefront).  MODE 1: Faure's permutation, built
-// from sigma_2 = (0, 1) up the chain of sizes (even y: 2 sigma_{y/2} then 2 sigma_{y/2} + 1;
-// odd y: sigma_{y-1} with values >= (y-1)/2 raised and (y-1)/2 in the middle).  MODE 2:
-// sigma(a) = f a mod b.  Returns the buffer that holds it.
+struct FaureTable {
+    uint16_t v[faure_total()];
+    uint16_t off[QMC_MAX_DIMS];  // start of base j's permutation in v
+};
+
+struct FaureAll {  // sigma_y for every y <= kMaxBase (compile-time scratch)
+    uint16_t p[kMaxBase + 1][kMaxBase + 1];
+};
+
+constexpr FaureTable make_faure_table() {
+    FaureAll all{};
+    all.p[2][1] = 1;
+    for (uint32_t y = 3; y <= kMaxBase; ++y) {
+        if (y % 2 == 0) {
+            const uint32_t h = y / 2;
+            for (uint32_t a = 0; a < h; ++a) {
+                all.p[y][a] = static_cast<uint16_t>(2 * all.p[h][a]);
+                all.p[y][a + h] = static_cast<uint16_t>(2 * all.p[h][a] + 1);
+            }
+        } else {
+            const uint32_t c = (y - 1) / 2;
+            for (uint32_t a = 0; a < y; ++a) {
+                if (a == c) {
+                    all.p[y][a] = static_cast<uint16_t>(c);
+                } else {
+                    const uint32_t t = all.p[y - 1][a < c ? a : a - 1];
+                    all.p[y][a] = static_cast<uint16_t>(t >= c ? t + 1 : t);
+                }
+            }
+        }
+    }
+    FaureTable t{};
+    uint32_t pos = 0;
+    for (uint32_t j = 0; j < QMC_MAX_DIMS; ++j) {
+        const uint32_t b = kPrimeList[j];
+        t.off[j] = static_cast<uint16_t>(pos);
+        for (uint32_t a = 0; a < b; ++a) t.v[pos++] = all.p[b][a];
+    }
+    return t;
+}
+
+__constant__ FaureTable kFaure = make_faure_table();
+
+// Digit permutation of dimension j (base b) into LDS (one wavefront).  MODE 1: Faure's
+// permutation, copied from the compile-time table; MODE 2: sigma(a) = f a mod b.  Returns the
+// buffer that holds it.
 template <uint32_t MODE>
-__device__ uint32_t* build_permutation(uint32_t b, uint32_t f, uint32_t (&buf)[2][kMaxBase + 1]) {
+__device__ uint32_t* build_permutation(uint32_t b, uint32_t f, uint32_t j, uint32_t (&buf)[2][kMaxBase + 1]) {
     const uint32_t lane = threadIdx.x;
     if constexpr (MODE == 2) {
         for (uint32_t a = lane; a < b; a += kWave) buf[0][a] = static_cast<uint32_t>((uint64_t(f) * a) % b);
-        __syncthreads();
-        return buf[0];
     } else {
-        uint32_t len = 0;
-        while (faure_chain(b, len) > 2) ++len;
-        if (lane < 2) buf[0][lane] = lane;
-        uint32_t cur = 0;
-        __syncthreads();
-        for (uint32_t k = len; k-- > 0;) {
-            const uint32_t y = faure_chain(b, k);
-            for (uint32_t a = lane; a < y; a += kWave) {
-                uint32_t v;
-                if (!(y & 1u)) {
-                    const uint32_t h = y >> 1;
-                    v = a < h ? 2u * buf[cur][a] : 2u * buf[cur][a - h] + 1u;
-                } else {
-                    const uint32_t c = (y - 1u) >> 1;
-                    if (a == c) {
-                        v = c;
-                    } else {
-                        const uint32_t t = buf[cur][a < c ? a : a - 1u];
-                        v = t >= c ? t + 1u : t;
-                    }
-                }
-                buf[cur ^ 1u][a] = v;
-            }
-            __syncthreads();
-            cur ^= 1u;
-        }
-        return buf[cur];
+        const uint32_t off = kFaure.off[j];
+        for (uint32_t a = lane; a < b; a += kWave) buf[0][a] = kFaure.v[off + a];
     }
+    __syncthreads();
+    return buf[0];
 }
 
 // floor(2^32 phi_{b,sigma}(i mod b^M)) for b >= 3.
@@ -765,7 +789,7 @@ __global__ __launch_bounds__(kWave) void halton_fast(uint32_t first, uint32_t n,
     const uint32_t f = MODE == 2 ? factors[j] : 1u;
     if (MODE == 2 && h.b == 2) h.zero2 = (f & 1u) ? 0u : 1u;
     const uint32_t* sig = nullptr;
-    if constexpr (MODE != 0) sig = build_permutation<MODE>(h.b, f, buf);
+    if constexpr (MODE != 0) sig = build_permutation<MODE>(h.b, f, j, buf);
     const uint32_t lane = threadIdx.x;
     const uint32_t cb = blockIdx.x * run;
     const uint32_t ce = min(cb + run, nchunks);
@@ -845,7 +869,7 @@ __global__ __launch_bounds__(kWave) void halton_general(uint32_t first, uint32_t
     const uint32_t f = MODE == 2 ? factors[j] : 1u;
     if (MODE == 2 && h.b == 2) h.zero2 = (f & 1u) ? 0u : 1u;
     const uint32_t* sig = nullptr;
-    if constexpr (MODE != 0) sig = build_permutation<MODE>(h.b, f, buf);
+    if constexpr (MODE != 0) sig = build_permutation<MODE>(h.b, f, j, buf);
     for (uint32_t o = blockIdx.x * kWave + threadIdx.x; o < n; o += gridDim.x * kWave) {
         const uint32_t v = halton_value<MODE>(first + o, h, sig);
         if constexpr (WU) ou[uint64_t(j) * ld + o] = v;
@@ -938,13 +962,9 @@ qmc_status validate_generation(const char* who, qmc_context ctx, const void* tab
 // Constants of halton_fast for the first s primes and runs of `run` chunks (see HaltonDim).
 void halton_table(uint32_t s, uint32_t run, HaltonTable* t) {
     const uint64_t min_le = (uint64_t(kChunk) * run - 1) / 62 + 1;  // high parts span <= 64 values
-    static const uint32_t primes[QMC_MAX_DIMS] = {
-        2,   3,   5,   7,   11,  13,  17,  19,  23,  29,  31,  37,  41,  43,  47,  53,  59,  61,  67,  71,  73,  79,
-        83,  89,  97,  101, 103, 107, 109, 113, 127, 131, 137, 139, 149, 151, 157, 163, 167, 173, 179, 181, 191, 193,
-        197, 199, 211, 223, 227, 229, 233, 239, 241, 251, 257, 263, 269, 271, 277, 281, 283, 293, 307, 311};
     const unsigned __int128 two64 = static_cast<unsigned __int128>(1) << 64;
     for (uint32_t j = 0; j < s; ++j) {
-        const uint64_t b = primes[j];
+        const uint64_t b = kPrimeList[j];
         uint64_t maxpow = b;
         while (maxpow * b <= 0xFFFFFFFFull) maxpow *= b;
         uint32_t e = 1;
