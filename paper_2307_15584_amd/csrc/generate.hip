@@ -1275,8 +1275,8 @@ extern "C" qmc_status qmc_generate_halton(qmc_context ctx, qmc_stream stream, ui
     const bool fast = (first % 4 == 0) && (ld % 4 == 0) && aligned16(out_u32) && aligned16(out_f32);
     const uint32_t first32 = static_cast<uint32_t>(first);
     const uint32_t nn = static_cast<uint32_t>(n);
-    // digit tables cost more to set up with permutations: longer runs amortise them
-    const uint32_t run = mode == QMC_HALTON_IDENTITY ? 4u : 8u;
+    // linear digit permutations are formed per wavefront: longer runs amortise them
+    const uint32_t run = mode == QMC_HALTON_LINEAR ? 8u : 4u;
     HaltonTable tab{};
     if (fast) halton_table(s, run, &tab);
     clear_launch_error();
