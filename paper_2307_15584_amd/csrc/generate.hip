@@ -1,8 +1,10 @@
 // Materialised point generation: digital sequences (Sec. 2.3, Eq. ts) and rank-1 lattice
 // sequences (Sec. 2.4, Eq. R1LS), randomised in integers and converted by
-// map_u32_to_unifloat (Sec. 2.1, Alg. 1).
+// map_u32_to_unifloat (Sec. 2.1, Alg. 1); the same with 64-bit indices and partitioned
+// enumeration (Sec. 2.5.1); point-major output; the Halton sequence (Sec. 2.2).
 //
-// Output is dimension-major, out[j*ld + (i - first)].  The fast kernels launch one wavefront
+// Output is dimension-major, out[j*ld + (i - first)], unless the point-major layout is asked
+// for (its kernels are described with them).  The fast kernels launch one wavefront
 // per (dimension, run of `cpw` chunks of 256 indices), in dimension-major order, so that the
 // wavefronts in flight at any moment write one narrow, advancing window of each output array:
 // the access order of a plain fill, which is what the HBM write path sustains best.  Each lane
