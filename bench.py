@@ -366,8 +366,10 @@ def pixel_workloads(torch, q, reps, progressive):
 
 def pmc_probe(torch, q):
     """A copy of exactly 1 GiB (reads 1 GiB, writes 1 GiB) followed by one scrambled-Sobol'
-    generation launch of the benchmark workload; each kernel runs once."""
-    from synth import cp_shifts, nus_seeds, sobol_direction_init
+    generation launch of the benchmark workload, then one launch each of the other 2^24 x 32
+    generation kernels (lattice, Halton with identity and Faure digits, partitioned 64-bit
+    Sobol' and lattice, point-major Sobol' and lattice), all writing u32 + float32."""
+    from synth import cp_shifts, lattice_vector, nus_seeds, sobol_direction_init
 
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -382,6 +384,22 @@ def pmc_probe(torch, q):
     torch.cuda.synchronize()
     q.qmc_generate_sobol(mats, 0, n, seeds, shifts, 0, out_u32=su, out_f32=sf)
     torch.cuda.synchronize()
+    gvec = q.from_u32(lattice_vector(s, 20, 3))
+    wide = q.from_u32(q.qmc_sobol_matrices_wide(s, sobol_direction_init(s, 0), 64))
+    others = [
+        lambda: q.qmc_generate_lattice(gvec, 0, n, shifts, 0, out_u32=su, out_f32=sf),
+        lambda: q.qmc_generate_halton(s, 0, n, q.QMC_HALTON_IDENTITY, None, out_u32=su, out_f32=sf),
+        lambda: q.qmc_generate_halton(s, 0, n, q.QMC_HALTON_FAURE, None, out_u32=su, out_f32=sf),
+        lambda: q.qmc_generate_sobol64(wide, 1 << 44, n, 8, 77, seeds, shifts, 0, out_u32=su, out_f32=sf),
+        lambda: q.qmc_generate_lattice64(gvec, 1 << 44, n, 8, 77, shifts, 0, out_u32=su, out_f32=sf),
+        lambda: q.qmc_generate_sobol(mats, 0, n, seeds, shifts, q.QMC_POINT_MAJOR, out_u32=su.view(n, s),
+                                     out_f32=sf.view(n, s), ld=s),
+        lambda: q.qmc_generate_lattice(gvec, 0, n, shifts, q.QMC_POINT_MAJOR, out_u32=su.view(n, s),
+                                       out_f32=sf.view(n, s), ld=s),
+    ]
+    for fn in others:
+        fn()
+        torch.cuda.synchronize()
     print("pmc probe done", flush=True)
 
 
