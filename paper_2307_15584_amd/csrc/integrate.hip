@@ -110,14 +110,26 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total) 
     return x - v;
 }
 
-// Inclusive scan of v over runs of equal `key` (runs are contiguous in lane order).
+// One step of the segmented scan below: v += the value of the lane DPP control CTRL names, when
+// that lane carries the same key (lanes without a source receive v = 0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float seg_step(float v, uint32_t key) {
+    const int vs = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false);
+    const int ks = __builtin_amdgcn_update_dpp(-1, static_cast<int>(key), CTRL, ROW_MASK, 0xF, false);
+    return static_cast<uint32_t>(ks) == key ? v + __int_as_float(vs) : v;
+}
+
+// Inclusive scan of v over runs of equal `key` (runs are contiguous in lane order), in DPP:
+// shifts by 1, 2, 4 and 8 within rows of 16 lanes, then the last lane of row 0 (2) into row 1
+// (3) and of row 1 into rows 2 and 3.  Each step adds a partial sum only across equal keys, and
+// since runs are contiguous the partial it adds covers exactly the earlier lanes of its run.
 __device__ __forceinline__ float segmented_scan(float v, uint32_t key) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const float y = __shfl_up(v, o, kWave);
-        const uint32_t ky = __shfl_up(key, o, kWave);
-        if (lane_id() >= static_cast<uint32_t>(o) && ky == key) v += y;
-    }
+    v = seg_step<0x111, 0xF>(v, key);  // row_shr 1
+    v = seg_step<0x112, 0xF>(v, key);  // row_shr 2
+    v = seg_step<0x114, 0xF>(v, key);  // row_shr 4
+    v = seg_step<0x118, 0xF>(v, key);  // row_shr 8
+    v = seg_step<0x142, 0xA>(v, key);  // row_bcast 15 into rows 1, 3
+    v = seg_step<0x143, 0xC>(v, key);  // row_bcast 31 into rows 2, 3
     return v;
 }
 
