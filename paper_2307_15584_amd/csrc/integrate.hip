@@ -99,6 +99,25 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// The same sum in DPP, without LDS: an inclusive scan (row shifts by 1, 2, 4, 8, then row
+// broadcasts of lanes 15 and 31) leaves the total in lane 63, which is returned to every lane.
+// Used where it measured faster: at the end of each big pixel of the Genz kernel (the lobe
+// kernels measured the same or slower with it).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+    v = dpp_add<0x111, 0xF>(v);
+    v = dpp_add<0x112, 0xF>(v);
+    v = dpp_add<0x114, 0xF>(v);
+    v = dpp_add<0x118, 0xF>(v);
+    v = dpp_add<0x142, 0xA>(v);
+    v = dpp_add<0x143, 0xC>(v);
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total) {
     uint32_t x = v;
 #pragma unroll
@@ -676,7 +695,7 @@ __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
                 }
             },
             [&](uint32_t q) {
-                const float t = wave_sum(big_acc);
+                const float t = wave_sum_dpp(big_acc);
                 const uint32_t nq = __builtin_amdgcn_readlane(n_own, q);
                 if (lane == 0) write_pixel_n(a, task * kTile + q, t, nq);
             },
