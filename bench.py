@@ -538,6 +538,12 @@ def main():
     lat_ms = _event_ms(torch, lambda: q.qmc_generate_lattice(gvec, 0, n, shifts, 0, out_u32=su, out_f32=sf), 20)
     out["lattice_2p24x32"] = {"kernel_ms": round(lat_ms, 4), "gbs": round(alg_bytes / (lat_ms * 1e-3) / 1e9, 1),
                               "frac": round(alg_bytes / (lat_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    # the same scrambled Sobol' workload written as u32 only (2.15 GB)
+    u32_ms = _event_ms(torch, lambda: q.qmc_generate_sobol(mats, 0, n, seeds, shifts, 0, out_u32=su, want_f32=False),
+                       10)
+    out["sobol_u32_only_2p24x32"] = {"kernel_ms": round(u32_ms, 4),
+                                     "gpts_dim_per_s": round(s * n / (u32_ms * 1e-3) / 1e9, 1),
+                                     "hbm_frac": round(alg_bytes / 2 / (u32_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     hal = {}
     for name, mode in (("identity", q.QMC_HALTON_IDENTITY), ("faure", q.QMC_HALTON_FAURE)):
         h_ms = _event_ms(torch, lambda: q.qmc_generate_halton(s, 0, n, mode, None, out_u32=su, out_f32=sf), 10)

@@ -987,6 +987,14 @@ void halton_table(uint32_t s, uint32_t run, HaltonTable* t) {
     }
 }
 
+// The tuned launch shape is for both outputs (2 KiB per chunk of 256 indices).  With one output
+// a chunk writes half as much, and one chunk per wavefront leaves the dispatch of wavefronts,
+// not HBM, as the limit: such launches take four times as many chunks per wavefront.
+GenTune launch_tune(GenTune tn, bool both_outputs) {
+    if (!both_outputs) tn.chunks_per_wave *= 4;
+    return tn;
+}
+
 // Grid of the fast kernels: x = runs of cpw chunks, y = dimension (dimension-major dispatch).
 dim3 fast_grid(uint64_t n, uint32_t s, const GenTune& tn, uint32_t* nchunks) {
     *nchunks = static_cast<uint32_t>((n + kChunk - 1) / kChunk);
@@ -1051,7 +1059,7 @@ extern "C" qmc_status qmc_generate_sobol(qmc_context ctx, qmc_stream stream, con
                     } else if (fast) {
                         with_bool(ctx->sobol_tune.nontemporal != 0, [&](auto NT) {
                             uint32_t nchunks;
-                            const GenTune& tn = ctx->sobol_tune;
+                            const GenTune tn = launch_tune(ctx->sobol_tune, WU.value && WF.value);
                             const dim3 grid = fast_grid(nn, s, tn, &nchunks);
                             hipLaunchKernelGGL((sobol_fast<NUS.value, SH.value, SX.value, WU.value, WF.value, NT.value>),
                                                grid, dim3(kWave), 0, hs, matrices, first32, nn, nus_seeds, shifts,
@@ -1107,7 +1115,7 @@ extern "C" qmc_status qmc_generate_lattice(qmc_context ctx, qmc_stream stream, c
                     } else if (fast) {
                         with_bool(ctx->lattice_tune.nontemporal != 0, [&](auto NT) {
                             uint32_t nchunks;
-                            const GenTune& tn = ctx->lattice_tune;
+                            const GenTune tn = launch_tune(ctx->lattice_tune, WU.value && WF.value);
                             const dim3 grid = fast_grid(nn, s, tn, &nchunks);
                             hipLaunchKernelGGL(
                                 (lattice_fast<BK.value, SH.value, SX.value, WU.value, WF.value, NT.value>), grid,
@@ -1183,7 +1191,7 @@ extern "C" qmc_status qmc_generate_sobol64(qmc_context ctx, qmc_stream stream, c
                         if (fast) {
                             with_bool(ctx->sobol_tune.nontemporal != 0, [&](auto NT) {
                                 uint32_t nchunks;
-                                const GenTune& tn = ctx->sobol_tune;
+                                const GenTune tn = launch_tune(ctx->sobol_tune, WU.value && WF.value);
                                 const dim3 grid = fast_grid(nn, s, tn, &nchunks);
                                 hipLaunchKernelGGL(
                                     (sobol64_fast<NUS.value, SH.value, SX.value, WU.value, WF.value, NT.value>), grid,
@@ -1232,7 +1240,7 @@ extern "C" qmc_status qmc_generate_lattice64(qmc_context ctx, qmc_stream stream,
                         if (fast) {
                             with_bool(ctx->lattice_tune.nontemporal != 0, [&](auto NT) {
                                 uint32_t nchunks;
-                                const GenTune& tn = ctx->lattice_tune;
+                                const GenTune tn = launch_tune(ctx->lattice_tune, WU.value && WF.value);
                                 const dim3 grid = fast_grid(nn, s, tn, &nchunks);
                                 hipLaunchKernelGGL(
                                     (lattice64_fast<BK.value, SH.value, SX.value, WU.value, WF.value, NT.value>), grid,
