@@ -163,8 +163,11 @@ def l2_loss(means, target):
     return math.fsum(d * d) / d.size
 
 
-def lobes_gradient(sampler, integrand, counts, pixels, grad_means, begin=0, end=2**32, theta=None):
-    """dL/dtheta = sum_p gI_p (1/N_p) sum_{i in window} df(x_pi)/dtheta, FP64 [L*(2d+1)]."""
+def lobes_gradient(sampler, integrand, counts, pixels, grad_means, begin=0, end=2**32, theta=None, sizes=False):
+    """dL/dtheta = sum_p gI_p (1/N_p) sum_{i in window} df(x_pi)/dtheta, FP64 [L*(2d+1)].
+
+    With sizes=True, the sum of the absolute values of those terms instead: the scale of what an
+    FP32 evaluation adds up, which bounds its rounding error (a test tolerance, not the method)."""
     pixels = np.asarray(pixels, dtype=np.int64)
     L, d = integrand["num_lobes"], integrand["d"]
     th = np.asarray(integrand["params"] if theta is None else theta, dtype=np.float64)
@@ -175,6 +178,8 @@ def lobes_gradient(sampler, integrand, counts, pixels, grad_means, begin=0, end=
     gm = np.asarray(grad_means, dtype=np.float64)
     pos = {int(q): k for k, q in enumerate(pixels)}
     scale = np.array([gm[pos[int(q)]] / n[int(q)] for q in p]) if p.size else np.zeros(0)
+    if sizes:
+        return lobes_weighted_gradient_abs(y, scale, th, L, d)
     return lobes_weighted_gradient(y, scale, th, L, d)
 
 

@@ -311,6 +311,48 @@ def test_full_size_lobes_forward_sampled_pixels(qmc):
     assert _est_tol(got[pix], ref).all()
 
 
+def test_full_size_progressive_sampled_pixels(qmc):
+    """The 3840x2160 progressive workload as timed: 16 graph-replayed passes of 64 spp, counts
+    64..1024, 32 lobes in 64 dims, NUS + shift.  Means at 300 sampled pixels vs FP64; then the
+    adjoint over the whole frame with dL/dI nonzero only at 48 sampled pixels vs the FP64
+    gradient of those pixels, within 1e-4 relative or 2e-5 of the size of the terms summed."""
+    import torch
+
+    from synth import counts_progressive
+
+    W, H, d, L = 3840, 2160, 64, 32
+    P = W * H
+    counts = counts_progressive(W, H, 5, passes=16, spp_per_pass=64)
+    theta, dtheta = _lobes_setup(qmc, L, d)
+    ds, os_ = _sampler_pair(qmc, "sobol", 64, 0xC5, NUS | SHIFT)
+    ig = qmc.PixelIntegrand.lobes(dtheta, L, d, 9)
+    oig = {"kind": "lobes", "d": d, "num_lobes": L, "params": theta, "pixel_seed": 9}
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    sums = torch.zeros(P, dtype=torch.float32, device="cuda")
+    means = torch.empty(P, dtype=torch.float32, device="cuda")
+    qmc.qmc_integrate_progressive(ds, ig, W, H, dc, 16, 64, sums, means, use_graph=True)
+    torch.cuda.synchronize()
+    pix = pick(P, 300, 44)
+    got = means[torch.from_numpy(pix).cuda()].cpu().numpy()
+    ref = estimator.integrate_pixels(os_, oig, counts, pix)
+    ok = _est_tol(got, ref)
+    assert ok.all(), (pix[~ok][:10], got[~ok][:5], ref["mean"][~ok][:5])
+    del sums, means
+
+    gpix = pick(P, 48, 45)
+    gvals = (np.random.default_rng(46).uniform(-1.0, 1.0, gpix.size) / gpix.size).astype(np.float32)
+    gm = torch.zeros(P, dtype=torch.float32, device="cuda")
+    gm[torch.from_numpy(gpix).cuda()] = torch.from_numpy(gvals).cuda()
+    g = qmc.qmc_integrate_pixels_backward(ds, ig, W, H, dc, gm)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    g64 = estimator.lobes_gradient(os_, oig, counts, gpix, gvals)
+    size = estimator.lobes_gradient(os_, oig, counts, gpix, gvals, sizes=True)
+    err = np.abs(g - g64)
+    ok = (err <= 1e-4 * np.abs(g64)) | (err <= 2e-5 * size)
+    assert ok.all(), (np.nonzero(~ok)[0][:10], g[~ok][:5], g64[~ok][:5], size[~ok][:5])
+
+
 def test_integration_argument_errors(qmc):
     import torch
 
