@@ -10,6 +10,8 @@ with seed_pj = H(H(seed + 2j) ^ p) and delta_pj = H(H(seed + 2j + 1) ^ p).  The 
 options of Sec. 3 (see pixel_lattice): g_j may be replaced by the per-pixel random generator
 g_pj (Alg. 4), optionally with four superimposed instances, and s_p is the pixel's Hilbert
 shift floor(2^32 phi_3(h(x, y))) (Eq. PixelShiftedR1LS), else 0.
+  XOR table (Sec. 2.6.1, see xor_table): v = P_j[(i XOR r_c) mod N] XOR s_cj for the pixel's
+  cell c in the 128 x 128 tables.
 
 A call covers the window of sample indices [begin, min(end, N_p)); the window sum is
 added to `sums` and the mean is sums / N_p.  The estimator I_p = (1/N_p) sum_i f_p(x_pi)
@@ -21,7 +23,7 @@ import math
 
 import numpy as np
 
-from . import digital, lattice, pixel_lattice, scramble, unifloat
+from . import digital, lattice, pixel_lattice, scramble, unifloat, xor_table
 from .integrands import genz, lobes, lobes_weighted_gradient, lobes_weighted_gradient_abs
 
 # Flag bits shared with the library's public header (values fixed by that interface).
@@ -53,6 +55,10 @@ def window_pairs(counts, pixels, begin, end):
 def pixel_samples_u32(sampler, p, i):
     """Integer sample components, uint32 [s][n], for pixel/index arrays p, i."""
     kind = sampler["kind"]
+    if kind == "xor_table":
+        # Sec. 2.6.1: stored points reindexed and scrambled per pixel from 128 x 128 tables
+        return xor_table.xor_table_samples_u32(sampler["table"], sampler["scramble"], sampler["reorder"],
+                                               sampler["width"], p, i)
     s = sampler["s"]
     flags = sampler.get("flags", 0)
     seed = sampler.get("seed", 0)
