@@ -243,6 +243,13 @@ qmc_status qmc_generate_lattice64(qmc_context ctx, qmc_stream stream,
  *     other diagonal), so that consecutive indices are edge-adjacent pixels.
  *   POINTS:  x = table[j * points_ld + offsets[p] + i] (samples materialised beforehand by
  *   qmc_generate_pixel_samples: the plain generate-then-integrate path).
+ *   XOR_TABLE (Sec. 2.6.1, image-plane decorrelation by XOR): one set of N stored integer
+ *     points P_j[k] = table[j * points_ld + k], N = points_ld a power of two, serves every
+ *     pixel; for the pixel's cell c = (y mod 128) * 128 + (x mod 128) of the 128 x 128 tables,
+ *     v = P_j[(i XOR xor_reorder[c]) mod N] XOR xor_scramble[j * 16384 + c], then
+ *     x = map_u32_to_unifloat(v).  The stored points (Owen-scrambled Sobol' points in the
+ *     paper, e.g. from qmc_generate_sobol with NUS) and both tables are the caller's; the
+ *     index is taken modulo N, so the stored points repeat with period N.  No flags.
  *
  * Integrands (FP32 on the GPU):
  *   QMC_F_GENZ (d = 8; pixel_params [P][16]: centres u_0..u_7 then widths a_0..a_7):
@@ -255,6 +262,8 @@ qmc_status qmc_generate_lattice64(qmc_context ctx, qmc_stream stream,
 #define QMC_SAMPLER_SOBOL 1u
 #define QMC_SAMPLER_LATTICE 2u
 #define QMC_SAMPLER_POINTS 3u
+#define QMC_SAMPLER_XOR_TABLE 4u
+#define QMC_XOR_TABLE_CELLS 16384u      /* 128 x 128 cells of the XOR_TABLE sampler's tables */
 
 #define QMC_PIXEL_NUS 4u                /* sampler flag: per-pixel nested uniform scramble (SOBOL) */
 #define QMC_PIXEL_SHIFT 8u              /* sampler flag: per-pixel rotation (addition, or XOR with QMC_SHIFT_XOR) */
@@ -269,13 +278,17 @@ typedef struct {
     uint32_t kind;           /* QMC_SAMPLER_*                                                     */
     uint32_t s;              /* dimensions in `table` (>= the integrand's d; <= QMC_MAX_DIMS)      */
     const void* table;       /* device: SOBOL u32 [s][32] matrices | LATTICE u32 [s] generator |   */
-                             /*         POINTS float32 [s][points_ld] samples                      */
-    uint64_t points_ld;      /* POINTS: leading dimension of table                                 */
+                             /*         POINTS float32 [s][points_ld] samples |                    */
+                             /*         XOR_TABLE u32 [s][points_ld] stored points                 */
+    uint64_t points_ld;      /* POINTS: leading dimension of table; XOR_TABLE: N, a power of two  */
+                             /*         in [1, 2^32]                                               */
     const uint64_t* offsets; /* POINTS: device [P], slot of sample 0 of pixel p                    */
     uint32_t seed;           /* per-pixel seeds and rotations are derived from this                */
     uint32_t flags;          /* QMC_PIXEL_NUS | QMC_PIXEL_SHIFT | QMC_SHIFT_XOR | QMC_LATTICE_BACKWARD  */
                              /* | QMC_PIXEL_RANDOM_GENERATOR | QMC_LATTICE_INSTANCES4                  */
                              /* | QMC_PIXEL_HILBERT_SHIFT (the last three: LATTICE only)              */
+    const uint32_t* xor_scramble; /* XOR_TABLE: device u32 [s][16384] digit scrambles s_cj         */
+    const uint32_t* xor_reorder;  /* XOR_TABLE: device u32 [16384] index reorderings r_c           */
 } qmc_sampler;
 
 typedef struct {
@@ -301,7 +314,8 @@ qmc_status qmc_workspace_size(qmc_context ctx, const qmc_sampler* sampler, const
  * order, so results are bitwise reproducible for a given launch configuration.
  *   counts: device u32 [width*height];  sums, means: device float32 [width*height];
  *   workspace: device, >= qmc_workspace_size(..., 0) bytes, no initial contents required.
- * Errors: INVALID_ARGUMENT (NULLs, sums and means both NULL, d > s, bad flags, begin > end),
+ * Errors: INVALID_ARGUMENT (NULLs, sums and means both NULL, d > s, bad flags, begin > end,
+ *         XOR_TABLE without its tables or with N not a power of two in [1, 2^32]),
  *         UNSUPPORTED (d not supported for the kind), WORKSPACE (too small). */
 qmc_status qmc_integrate_pixels(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
                                 const qmc_integrand* integrand, uint32_t width, uint32_t height,
@@ -346,7 +360,7 @@ qmc_status qmc_sample_offsets(qmc_context ctx, qmc_stream stream, const uint32_t
 
 /* The plain path's first half: writes sample i < N_p of pixel p, dimension j < d, as
  * out[j * ld + offsets[p] + i] (float32), exactly the values the fused integration uses
- * (before any integrand offset).  sampler: SOBOL or LATTICE.  offsets: from
+ * (before any integrand offset).  sampler: SOBOL, LATTICE or XOR_TABLE.  offsets: from
  * qmc_sample_offsets; ld >= offsets[P]; out: device float32 [d][ld].
  * workspace: >= 256 bytes of device memory (a work counter). */
 qmc_status qmc_generate_pixel_samples(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler, uint32_t d,

@@ -30,6 +30,8 @@ from ._lib import (  # noqa: F401
     QMC_SAMPLER_LATTICE,
     QMC_SAMPLER_POINTS,
     QMC_SAMPLER_SOBOL,
+    QMC_SAMPLER_XOR_TABLE,
+    QMC_XOR_TABLE_CELLS,
     QMC_SHIFT_XOR,
     Integrand,
     QMCError,
@@ -269,18 +271,20 @@ def qmc_generate_halton(s, first, n, mode=0, factors=None, out_u32=None, out_f32
 class PixelSampler:
     """A qmc_sampler plus the device tensors it points to (kept alive with it)."""
 
-    def __init__(self, kind, table, seed=0, flags=0, points_ld=0, offsets=None, s=None):
+    def __init__(self, kind, table, seed=0, flags=0, points_ld=0, offsets=None, s=None, xor_scramble=None,
+                 xor_reorder=None):
         self.table = table
         self.offsets = offsets
+        self.xor_scramble, self.xor_reorder = xor_scramble, xor_reorder
         self.kind = kind
         self.seed = seed
         self.flags = flags
         if s is None:
             s = table.shape[0]
         self.s = s
-        self.c = Sampler(kind, s, _dev_ptr(table, "table").value, points_ld,
-                         _dev_ptr(offsets, "offsets").value if offsets is not None else None, seed & 0xFFFFFFFF,
-                         flags)
+        opt = lambda t, name: _dev_ptr(t, name).value if t is not None else None
+        self.c = Sampler(kind, s, _dev_ptr(table, "table").value, points_ld, opt(offsets, "offsets"),
+                         seed & 0xFFFFFFFF, flags, opt(xor_scramble, "xor_scramble"), opt(xor_reorder, "xor_reorder"))
 
     @classmethod
     def sobol(cls, matrices, seed, flags=QMC_PIXEL_NUS | QMC_PIXEL_SHIFT):
@@ -291,6 +295,17 @@ class PixelSampler:
     @classmethod
     def lattice(cls, generator, seed, flags=QMC_PIXEL_SHIFT):
         return cls(QMC_SAMPLER_LATTICE, generator, seed, flags)
+
+    @classmethod
+    def xor_table(cls, points, scramble, reorder):
+        """Stored points u32 [s][N] (N a power of two), digit scrambles u32 [s][16384] and index
+        reorderings u32 [16384] of the 128 x 128 pixel tables (Sec. 2.6.1)."""
+        s, n = points.shape
+        if n == 0 or n & (n - 1) or n > 1 << 32:
+            raise ValueError("the number of stored points must be a power of two <= 2^32")
+        if tuple(scramble.shape) != (s, QMC_XOR_TABLE_CELLS) or reorder.numel() != QMC_XOR_TABLE_CELLS:
+            raise ValueError("scramble must be [s][16384] and reorder [16384]")
+        return cls(QMC_SAMPLER_XOR_TABLE, points, 0, 0, points_ld=n, s=s, xor_scramble=scramble, xor_reorder=reorder)
 
     @classmethod
     def points(cls, samples, offsets):

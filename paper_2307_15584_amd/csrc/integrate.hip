@@ -56,6 +56,11 @@ struct Args {
     const float* points;
     uint64_t points_ld;
     const uint64_t* offsets;
+    // table-driven XOR sampler (Sec. 2.6.1): digit scrambles [s][cells], index reorderings
+    // [cells], and N - 1 for the N stored points in `table`
+    const uint32_t* xor_scramble;
+    const uint32_t* xor_reorder;
+    uint32_t xor_mask;
     // integrand
     uint32_t fkind, d, L, pixel_seed;
     const float* params;        // theta (lobes)
@@ -357,7 +362,19 @@ __device__ __forceinline__ void sample_point(float (&x)[kGen<D>], const SamplerL
                                              const uint32_t* base, bool valid, uint32_t j0,
                                              const PackedSeeds<D>* PK = nullptr, uint32_t q = 0) {
     constexpr int G = kGen<D>;
-    if constexpr (SK == QMC_SAMPLER_POINTS) {
+    if constexpr (SK == QMC_SAMPLER_XOR_TABLE) {
+        // the pixel's cell of the 128 x 128 tables; stored point (i ^ r_c) mod N, digits ^ s_cj
+        const uint32_t y = p / a.width, xc = p - y * a.width;
+        const uint32_t c = ((y & 127u) << 7) | (xc & 127u);
+        const uint32_t idx = valid ? ((i ^ a.xor_reorder[c]) & a.xor_mask) : 0u;
+#pragma unroll
+        for (int jj = 0; jj < G; ++jj) {
+            const uint32_t j = j0 + jj;
+            x[jj] = (valid && j < a.d) ? dev::u32_to_unifloat(a.table[uint64_t(j) * a.points_ld + idx] ^
+                                                              a.xor_scramble[j * QMC_XOR_TABLE_CELLS + c])
+                                       : 0.0f;
+        }
+    } else if constexpr (SK == QMC_SAMPLER_POINTS) {
         const uint64_t off = valid ? a.offsets[p] + i : 0;
 #pragma unroll
         for (int jj = 0; jj < G; ++jj)
@@ -1252,8 +1269,16 @@ Plan make_plan(const qmc_integrand* ig, uint32_t P, int mode) {
 }
 
 qmc_status validate_sampler(const char* who, const qmc_sampler* sp, uint32_t d) {
-    if (sp->kind < QMC_SAMPLER_SOBOL || sp->kind > QMC_SAMPLER_POINTS)
+    if (sp->kind < QMC_SAMPLER_SOBOL || sp->kind > QMC_SAMPLER_XOR_TABLE)
         return fail(QMC_ERR_INVALID_ARGUMENT, "%s: unknown sampler kind %u", who, sp->kind);
+    if (sp->kind == QMC_SAMPLER_XOR_TABLE) {
+        if (sp->flags) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: the XOR table sampler takes no flags", who);
+        if (!sp->xor_scramble || !sp->xor_reorder)
+            return fail(QMC_ERR_INVALID_ARGUMENT, "%s: XOR table sampler needs its scramble and reorder tables", who);
+        const uint64_t n = sp->points_ld;
+        if (n == 0 || n > (uint64_t(1) << 32) || (n & (n - 1)))
+            return fail(QMC_ERR_INVALID_ARGUMENT, "%s: XOR table sampler needs 2^k stored points, k <= 32", who);
+    }
     if (!sp->table) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: sampler table is NULL", who);
     if (sp->s == 0 || sp->s > QMC_MAX_DIMS) return fail(QMC_ERR_OUT_OF_RANGE, "%s: sampler s out of range", who);
     const uint32_t lattice_only = QMC_PIXEL_RANDOM_GENERATOR | QMC_LATTICE_INSTANCES4 | QMC_PIXEL_HILBERT_SHIFT;
@@ -1308,7 +1333,7 @@ qmc_status validate(const char* who, qmc_context ctx, const qmc_sampler* sp, con
 
 // Launches Fam::go<SK, NUS, SHIFT, BACK> for the sampler's kind and flags; only the
 // meaningful combinations are instantiated (scrambling for Sobol' only, backward order for
-// the lattice only, materialised points without either).
+// the lattice only, materialised points and the XOR table sampler without either).
 template <typename Fam>
 void dispatch_sampler(uint32_t skind, bool nus, bool shift, bool back, uint32_t grid, hipStream_t hs, const Args& a) {
     if (skind == QMC_SAMPLER_SOBOL) {
@@ -1327,6 +1352,8 @@ void dispatch_sampler(uint32_t skind, bool nus, bool shift, bool back, uint32_t 
             if (shift) Fam::template go<QMC_SAMPLER_LATTICE, false, true, false>(grid, hs, a);
             else Fam::template go<QMC_SAMPLER_LATTICE, false, false, false>(grid, hs, a);
         }
+    } else if (skind == QMC_SAMPLER_XOR_TABLE) {
+        Fam::template go<QMC_SAMPLER_XOR_TABLE, false, false, false>(grid, hs, a);
     } else if constexpr (Fam::kPoints) {
         Fam::template go<QMC_SAMPLER_POINTS, false, false, false>(grid, hs, a);
     }
@@ -1400,6 +1427,9 @@ Args base_args(const qmc_sampler* sp, uint32_t d, uint32_t W, uint32_t H, const 
     a.points = static_cast<const float*>(sp->table);
     a.points_ld = sp->points_ld;
     a.offsets = sp->offsets;
+    a.xor_scramble = sp->xor_scramble;
+    a.xor_reorder = sp->xor_reorder;
+    a.xor_mask = static_cast<uint32_t>(sp->points_ld - 1);
     a.d = d;
     a.num_pixels = P;
     a.counts = counts;

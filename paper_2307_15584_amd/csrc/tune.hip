@@ -237,7 +237,9 @@ extern "C" qmc_status qmc_integrate_progressive(qmc_context ctx, qmc_stream stre
     const IntegrateTune& tn = integrate_tune(ctx, integrand->kind, integrand->d, false);
     std::vector<uint64_t> key = {
         sampler->kind, sampler->s, reinterpret_cast<uint64_t>(sampler->table), sampler->points_ld,
-        reinterpret_cast<uint64_t>(sampler->offsets), sampler->seed, sampler->flags, integrand->kind, integrand->d,
+        reinterpret_cast<uint64_t>(sampler->offsets), sampler->seed, sampler->flags,
+        reinterpret_cast<uint64_t>(sampler->xor_scramble), reinterpret_cast<uint64_t>(sampler->xor_reorder),
+        integrand->kind, integrand->d,
         integrand->num_lobes, integrand->pixel_seed, reinterpret_cast<uint64_t>(integrand->params),
         reinterpret_cast<uint64_t>(integrand->pixel_params), width, height, reinterpret_cast<uint64_t>(counts),
         passes, spp_per_pass, reinterpret_cast<uint64_t>(sums), reinterpret_cast<uint64_t>(means),

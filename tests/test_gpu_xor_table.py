@@ -1,0 +1,181 @@
+"""GPU parity of the table-driven per-pixel XOR sampler (Sec. 2.6.1): materialised samples bit
+for bit against the oracle, the fused forward, adjoint and L2 step against FP64, a 1920x1080
+frame at sampled pixels, and argument errors.  Images wider or taller than 128 pixels make the
+tables repeat; sample counts above N make the stored points repeat; reorder entries span all
+32 bits, so the index is reduced modulo N."""
+
+import numpy as np
+import pytest
+
+from oracle import digital, estimator, scramble
+from synth import counts_uniform, genz_params, lobe_params, nus_seeds, perturb, pick, sobol_direction_init, u32_draws
+
+pytestmark = pytest.mark.gpu
+
+CELLS = 16384
+
+
+def _est_tol(got, ref):
+    env = np.maximum(np.abs(ref["mean"]), ref["env"])
+    floor = 1e-6 * max(float(np.max(ref["env"])), 1e-300)
+    return np.abs(got.astype(np.float64) - ref["mean"]) <= 2e-5 * np.maximum(env, floor)
+
+
+def _counts_edge(P):
+    base = np.array([0, 1, 2, 3, 63, 64, 65, 127, 128, 129, 200, 256, 5, 31, 32, 33, 1000], dtype=np.uint32)
+    return np.resize(base, P)
+
+
+def _stored_points(s, N, seed):
+    """N Owen-scrambled (nested uniform scramble) Sobol' points, u32 [s][N]."""
+    mats = digital.sobol_matrices(s, sobol_direction_init(s, 0))
+    seeds = nus_seeds(s, seed)
+    return np.stack([scramble.nested_uniform_scramble(digital.digital_point(mats[j], np.arange(N, dtype=np.uint64)),
+                                                      int(seeds[j])) for j in range(s)]).astype(np.uint32)
+
+
+def _pair(q, s, N, seed, W):
+    import torch
+
+    pts = _stored_points(s, N, seed)
+    scr = u32_draws(seed + 100, s * CELLS).reshape(s, CELLS)
+    reo = u32_draws(seed + 200, CELLS)
+    dev = q.PixelSampler.xor_table(q.from_u32(pts), q.from_u32(scr), q.from_u32(reo))
+    ora = {"kind": "xor_table", "s": s, "table": pts, "scramble": scr, "reorder": reo, "width": W}
+    return dev, ora
+
+
+def _all_pairs(counts):
+    c = counts.astype(np.int64)
+    return np.repeat(np.arange(c.size), c), np.concatenate([np.arange(n) for n in c])
+
+
+@pytest.mark.parametrize("W,H,d,N", [(131, 4, 8, 256), (6, 130, 40, 64), (129, 2, 3, 1)])
+def test_materialised_samples_bit_exact(qmc, W, H, d, N):
+    import torch
+
+    P = W * H
+    counts = _counts_edge(P)
+    ds, os_ = _pair(qmc, d, N, 3, W)
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    offs = qmc.qmc_sample_offsets(dc)
+    total = int(counts.astype(np.int64).sum())
+    pts = qmc.qmc_generate_pixel_samples(ds, d, W, H, dc, offs, total)
+    torch.cuda.synchronize()
+    p_arr, i_arr = _all_pairs(counts)
+    want = estimator.pixel_samples_f32(os_, p_arr, i_arr)
+    assert np.array_equal(pts.cpu().numpy().view(np.uint32), want.view(np.uint32))
+
+
+def _genz(q, sampler, W, H, counts, pp):
+    import torch
+
+    ig = q.PixelIntegrand.genz(torch.from_numpy(pp).cuda())
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    m = q.qmc_integrate_pixels(sampler, ig, W, H, dc)
+    torch.cuda.synchronize()
+    return m.cpu().numpy()
+
+
+def test_genz_forward_and_plain_equals_fused(qmc):
+    import torch
+
+    W, H = 131, 4
+    P = W * H
+    counts = _counts_edge(P)
+    ds, os_ = _pair(qmc, 8, 256, 5, W)
+    pp = genz_params(P, 4)
+    got = _genz(qmc, ds, W, H, counts, pp)
+    ref = estimator.integrate_pixels(os_, {"kind": "genz", "d": 8, "pixel_params": pp}, counts, range(P))
+    ok = _est_tol(got, ref)
+    assert ok.all(), (np.nonzero(~ok)[0][:10], got[~ok][:5], ref["mean"][~ok][:5])
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    offs = qmc.qmc_sample_offsets(dc)
+    pts = qmc.qmc_generate_pixel_samples(ds, 8, W, H, dc, offs, int(counts.astype(np.int64).sum()))
+    plain = _genz(qmc, qmc.PixelSampler.points(pts, offs), W, H, counts, pp)
+    assert np.array_equal(got.view(np.uint32), plain.view(np.uint32))
+
+
+@pytest.mark.parametrize("d,L,W,H,N", [(8, 64, 131, 2, 128), (40, 7, 3, 130, 64)])
+def test_lobes_forward(qmc, d, L, W, H, N):
+    import torch
+
+    P = W * H
+    counts = _counts_edge(P)
+    theta = lobe_params(L, d, 6)
+    ds, os_ = _pair(qmc, d, N, 7, W)
+    ig = qmc.PixelIntegrand.lobes(torch.from_numpy(theta).cuda(), L, d, 9)
+    got = qmc.qmc_integrate_pixels(ds, ig, W, H, torch.from_numpy(counts.view(np.int32)).cuda()).cpu().numpy()
+    ref = estimator.integrate_pixels(os_, {"kind": "lobes", "d": d, "num_lobes": L, "params": theta,
+                                           "pixel_seed": 9}, counts, range(P))
+    assert _est_tol(got, ref).all()
+
+
+@pytest.mark.parametrize("d,L,W,H", [(8, 64, 131, 2), (64, 32, 5, 2)])
+def test_adjoint_and_l2_step(qmc, d, L, W, H):
+    """dL/dtheta of the adjoint and of the fused L2 step against the FP64 analytic gradient."""
+    import torch
+
+    P = W * H
+    counts = counts_uniform(W, H, 64) if d == 64 else _counts_edge(P)
+    theta = lobe_params(L, d, 6)
+    ds, os_ = _pair(qmc, d, 128, 11, W)
+    ig = qmc.PixelIntegrand.lobes(torch.from_numpy(theta).cuda(), L, d, 9)
+    oig = {"kind": "lobes", "d": d, "num_lobes": L, "params": theta, "pixel_seed": 9}
+    target = estimator.integrate_pixels(os_, dict(oig, params=perturb(theta, 7)), counts, range(P))["mean"]
+    loss64, g64, means64 = estimator.loss_and_gradient(os_, oig, counts, range(P), target)
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    gm = (2.0 * (means64 - target) / P).astype(np.float32)
+    g = qmc.qmc_integrate_pixels_backward(ds, ig, W, H, dc, torch.from_numpy(gm).cuda())
+    means, loss, g2 = qmc.qmc_integrate_pixels_l2_step(ds, ig, W, H, dc,
+                                                       torch.from_numpy(target.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    scale = np.max(np.abs(g64))
+    for got in (g.cpu().numpy().astype(np.float64), g2.cpu().numpy().astype(np.float64)):
+        ok = np.abs(got - g64) <= 1e-4 * np.maximum(np.abs(g64), 1e-3 * scale)
+        assert ok.all(), (np.nonzero(~ok)[0][:10], got[~ok][:5], g64[~ok][:5])
+    assert abs(float(loss.cpu()[0]) - loss64) <= 1e-4 * loss64
+
+
+def test_full_size_genz_sampled_pixels(qmc):
+    """1920x1080 x 64 spp from 4096 stored 8-dimensional points; 800 sampled pixels vs FP64."""
+    W, H = 1920, 1080
+    P = W * H
+    counts = counts_uniform(W, H, 64)
+    ds, os_ = _pair(qmc, 8, 4096, 13, W)
+    pp = genz_params(P, 4)
+    got = _genz(qmc, ds, W, H, counts, pp)
+    pix = pick(P, 800, 47)
+    ref = estimator.integrate_pixels(os_, {"kind": "genz", "d": 8, "pixel_params": pp}, counts, pix)
+    ok = _est_tol(got[pix], ref)
+    assert ok.all(), (pix[~ok][:10], got[pix][~ok][:5], ref["mean"][~ok][:5])
+
+
+def test_argument_errors(qmc):
+    import torch
+
+    s, N = 8, 64
+    pts = qmc.from_u32(_stored_points(s, N, 1))
+    scr = qmc.from_u32(u32_draws(1, s * CELLS).reshape(s, CELLS))
+    reo = qmc.from_u32(u32_draws(2, CELLS))
+    ig = qmc.PixelIntegrand.genz(torch.from_numpy(genz_params(16, 4)).cuda())
+    dc = torch.full((16,), 8, dtype=torch.int32, device="cuda")
+
+    def status(sampler):
+        with pytest.raises(qmc.QMCError) as e:
+            qmc.qmc_integrate_pixels(sampler, ig, 4, 4, dc)
+        return e.value.status
+
+    X = qmc.QMC_SAMPLER_XOR_TABLE
+    assert status(qmc.PixelSampler(X, pts, 0, qmc.QMC_PIXEL_SHIFT, N, None, s, scr, reo)) == 1   # no flags
+    assert status(qmc.PixelSampler(X, pts, 0, 0, 48, None, s, scr, reo)) == 1                   # N not 2^k
+    assert status(qmc.PixelSampler(X, pts, 0, 0, 0, None, s, scr, reo)) == 1
+    assert status(qmc.PixelSampler(X, pts, 0, 0, N, None, s, None, reo)) == 1                    # no tables
+    assert status(qmc.PixelSampler(X, pts, 0, 0, N, None, s, scr, None)) == 1
+    with pytest.raises(ValueError):
+        qmc.PixelSampler.xor_table(pts[:, :48].contiguous(), scr, reo)
+    with pytest.raises(ValueError):
+        qmc.PixelSampler.xor_table(pts, scr[:, :100].contiguous(), reo)
+    ok = qmc.qmc_integrate_pixels(qmc.PixelSampler.xor_table(pts, scr, reo), ig, 4, 4, dc)
+    torch.cuda.synchronize()
+    assert ok.shape == (16,)
