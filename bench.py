@@ -11,7 +11,8 @@ GPU before timing starts.  Prints one JSON line.
 The same line carries the per-pixel integration workloads ("pixels"): the fused kernels
 (generate + evaluate + reduce in one launch, and the adjoint that recomputes samples) timed
 next to the plain path (materialise the per-pixel samples in HBM, then integrate them):
-  * Genz, 1920x1080 pixels, 2^k samples per pixel (k in 0..8 from a smooth map), d = 8;
+  * Genz, 1920x1080 pixels, 2^k samples per pixel (k in 0..8 from a smooth map), d = 8, also
+    under the lattice samplers of Sec. 3 and the table-driven XOR sampler of Sec. 2.6.1;
   * Gaussian lobes, 1920x1080 x 64 spp, d = 8, 64 lobes: forward + L2-loss gradient +
     adjoint ("fwd+bwd").
   * the 3840x2160 progressive run: 16 graph-captured passes of 64 spp, d = 64, 32 lobes,
@@ -220,7 +221,7 @@ def pixel_workloads(torch, q, reps, progressive):
     import numpy as np
 
     from synth import counts_pow2, counts_progressive, counts_uniform, genz_params, lattice_vector, lobe_params
-    from synth import sobol_direction_init
+    from synth import nus_seeds, sobol_direction_init, u32_draws
 
     out = {}
     W, H = 1920, 1080
@@ -263,6 +264,14 @@ def pixel_workloads(torch, q, reps, progressive):
         ms = _timed(torch, lambda: q.qmc_integrate_pixels(smp, ig3, W, H, dc3, means=means, workspace=ws3), reps)
         lat[name] = {"fused_ms": round(ms, 4), "fused_pixel_samples_per_s": round(n3 / (ms * 1e-3), 1)}
     out["genz_1920x1080_uneven"]["lattice_samplers"] = lat
+    # and under the table-driven XOR sampler of Sec. 2.6.1: 4096 stored scrambled Sobol' points
+    # (made by the library's own generator), 128 x 128 reorder and scramble tables
+    stored, _ = q.qmc_generate_sobol(m8, 0, 4096, q.from_u32(nus_seeds(8, 1)), None, want_f32=False)
+    xs = q.PixelSampler.xor_table(stored, q.from_u32(u32_draws(21, 8 * q.QMC_XOR_TABLE_CELLS).reshape(8, -1)),
+                                  q.from_u32(u32_draws(22, q.QMC_XOR_TABLE_CELLS)))
+    ms = _timed(torch, lambda: q.qmc_integrate_pixels(xs, ig3, W, H, dc3, means=means, workspace=ws3), reps)
+    out["genz_1920x1080_uneven"]["xor_table_sampler"] = {
+        "stored_points": 4096, "fused_ms": round(ms, 4), "fused_pixel_samples_per_s": round(n3 / (ms * 1e-3), 1)}
     del pts3
 
     # Gaussian lobes, forward + L2 gradient + adjoint
