@@ -23,8 +23,9 @@ Modules:
               permutations, and the Halton sequence (Sec. 2.2)
   partition   64-bit indices (wide Sobol' matrices, 64-digit lattice) and the partitioned
               enumeration of one sequence across processing elements (Sec. 2.5.1)
-  xor_table   the table-driven per-pixel sampler of Sec. 2.6.1: stored points, a per-pixel
-              index reordering and digit scramble from 128 x 128 tables, both by XOR
+  xor_table   the table-driven per-pixel samplers of Sec. 2.6.1: stored points with a
+              per-pixel index reordering and digit scramble by XOR, and per-pixel rotations
+              from one 128 x 128 table of two-dimensional shifts
   integrands  Genz and Gaussian-lobe integrands and their parameter gradients
   estimator   per-pixel QMC integro-approximation, loss, analytic and
               finite-difference gradients (Sec. 2.5)

@@ -10,6 +10,8 @@ with seed_pj = H(H(seed + 2j) ^ p) and delta_pj = H(H(seed + 2j + 1) ^ p).  The 
 options of Sec. 3 (see pixel_lattice): g_j may be replaced by the per-pixel random generator
 g_pj (Alg. 4), optionally with four superimposed instances, and s_p is the pixel's Hilbert
 shift floor(2^32 phi_3(h(x, y))) (Eq. PixelShiftedR1LS), else 0.
+  With PIXEL_TABLE_SHIFT the rotation delta_pj is entry j mod 2 of the pixel's cell in a
+  128 x 128 table of two-dimensional shifts (Sec. 2.6.1, see xor_table).
   XOR table (Sec. 2.6.1, see xor_table): v = P_j[(i XOR r_c) mod N] XOR s_cj for the pixel's
   cell c in the 128 x 128 tables.
 
@@ -34,6 +36,7 @@ PIXEL_SHIFT = 8
 PIXEL_RANDOM_GENERATOR = 16
 PIXEL_HILBERT_SHIFT = 32
 LATTICE_INSTANCES4 = 64
+PIXEL_TABLE_SHIFT = 256
 
 
 def window_pairs(counts, pixels, begin, end):
@@ -76,7 +79,10 @@ def pixel_samples_u32(sampler, p, i):
         else:
             raise ValueError(kind)
         if flags & PIXEL_SHIFT:
-            d = scramble.pixel_shift(seed, p, j)
+            if flags & PIXEL_TABLE_SHIFT:
+                d = xor_table.table_shift(sampler["shift_table"], sampler["width"], p, j)
+            else:
+                d = scramble.pixel_shift(seed, p, j)
             v = scramble.shift_xor(v, d) if flags & SHIFT_XOR else scramble.shift_add(v, d)
         out[j] = v.astype(np.uint32)
     return out

@@ -1,4 +1,4 @@
-"""The table-driven per-pixel sampler of Sec. 2.6.1 (image-plane decorrelation by XOR) — test
+"""The table-driven per-pixel samplers of Sec. 2.6.1 (image-plane decorrelation) — test
 infrastructure.
 
 One set of N stored s-dimensional integer points P = (p_0, ..., p_{N-1}) (in the paper,
@@ -15,6 +15,12 @@ an r_c >= N acts through its low bits.  For i < N and r_c < N the reduction chan
 
 The tables themselves (found by simulated annealing in the paper) are inputs; any tables of
 the right shape give a valid sampler.
+
+Table of rotations.  The second sampler of the section keeps the sequence (a rank-1 lattice
+sequence in the paper) and rotates it per pixel by a two-dimensional shift read from one
+128 x 128 table, the same vector for every pair of dimensions: component j of the pixel in
+cell c is rotated by t_{c, j mod 2} (integer rotation mod 2^32, or XOR), in place of the
+hashed per-pixel rotation.
 """
 
 import numpy as np
@@ -48,3 +54,9 @@ def xor_table_samples_u32(points, scramble_table, reorder, width, p, i):
 
 def xor_table_samples_f32(points, scramble_table, reorder, width, p, i):
     return unifloat.map_u32_to_unifloat(xor_table_samples_u32(points, scramble_table, reorder, width, p, i))
+
+
+def table_shift(shift_table, width, p, j):
+    """The rotation of component j for pixels p: entry j mod 2 of the cell's shift vector;
+    shift_table is uint32 [2][128^2]."""
+    return np.asarray(shift_table, dtype=np.uint64)[j % 2][pixel_cell(p, width)]

@@ -103,3 +103,55 @@ def test_estimator_uses_the_table_sampler():
     p, i = np.array([0, 7, 119]), np.array([5, 200, 127])
     assert np.array_equal(estimator.pixel_samples_u32(sp, p, i),
                           xor_table.xor_table_samples_u32(pts, scr, reo, W, p, i))
+
+
+def _lattice_sampler(s, W, table, flags=estimator.PIXEL_SHIFT | estimator.PIXEL_TABLE_SHIFT):
+    from synth import lattice_vector
+
+    g = lattice_vector(s, 20, 3)
+    return g, {"kind": "lattice", "s": s, "table": g, "seed": 0, "flags": flags, "width": W, "height": 4,
+               "shift_table": table}
+
+
+def test_constant_shift_table_is_a_global_rotation():
+    """All cells holding (a, b): the lattice rotated by (a, b, a, b, ...) (the generator's own
+    rotation path); with XOR, the digital shift."""
+    from oracle import generate
+
+    s, W, n = 5, 300, 64
+    a, b = 0x9E3779B9, 0x12345678
+    table = np.stack([np.full(xor_table.CELLS, a, np.uint32), np.full(xor_table.CELLS, b, np.uint32)])
+    for xor in (0, estimator.SHIFT_XOR):
+        g, sp = _lattice_sampler(s, W, table, estimator.PIXEL_SHIFT | estimator.PIXEL_TABLE_SHIFT | xor)
+        want, _ = generate.generate_lattice(g, 0, n, np.array([a, b, a, b, a], np.uint32), xor)
+        for pp in (0, 1000):
+            got = estimator.pixel_samples_u32(sp, np.full(n, pp), np.arange(n))
+            assert np.array_equal(got, want), (xor, pp)
+
+
+def test_shift_table_pairs_of_dimensions_and_tiling():
+    s, W, n = 6, 400, 32
+    table = u32_draws(60, 2 * xor_table.CELLS).reshape(2, xor_table.CELLS)
+    g, sp = _lattice_sampler(s, W, table)
+    _, plain = _lattice_sampler(s, W, table, 0)
+    i = np.arange(n)
+    f = lambda x, y: estimator.pixel_samples_u32(sp, np.full(n, y * W + x), i).astype(np.uint64)
+    base = estimator.pixel_samples_u32(plain, np.zeros(n, np.int64), i).astype(np.uint64)
+    a = f(7, 3)
+    d = (a - base) & np.uint64(0xFFFFFFFF)       # the rotation of each component
+    assert all(len(set(d[j].tolist())) == 1 for j in range(s))
+    assert d[0, 0] == d[2, 0] == d[4, 0] and d[1, 0] == d[3, 0] == d[5, 0]
+    assert d[0, 0] == table[0][3 * 128 + 7] and d[1, 0] == table[1][3 * 128 + 7]
+    assert np.array_equal(a, f(7 + 128, 3 + 256)) and not np.array_equal(a, f(8, 3))
+
+
+def test_rotated_lattice_keeps_one_point_per_interval():
+    """A rotated rank-1 lattice with odd generator components: each pixel's first 2^m points have
+    one coordinate in every interval [k/2^m, (k+1)/2^m) in every dimension."""
+    s, W, m = 4, 200, 7
+    table = u32_draws(61, 2 * xor_table.CELLS).reshape(2, xor_table.CELLS)
+    _, sp = _lattice_sampler(s, W, table)
+    for pp in (0, 129, 4321):
+        got = estimator.pixel_samples_u32(sp, np.full(1 << m, pp), np.arange(1 << m))
+        for j in range(s):
+            assert len(set((got[j] >> np.uint32(32 - m)).tolist())) == 1 << m, (pp, j)
