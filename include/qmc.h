@@ -227,6 +227,9 @@ qmc_status qmc_generate_lattice64(qmc_context ctx, qmc_stream stream,
  *            unless QMC_PIXEL_RANDOM_GENERATOR (below);
  *   then v = v + delta_pj mod 2^32 with QMC_PIXEL_SHIFT (v ^ delta_pj with QMC_SHIFT_XOR),
  *   and x = map_u32_to_unifloat(v).
+ *   QMC_PIXEL_TABLE_SHIFT (with QMC_PIXEL_SHIFT; Sec. 2.6.1, one table of two-dimensional
+ *     rotations repeated for all pairs of dimensions): delta_pj = shift_table[(j mod 2) *
+ *     16384 + c] for the pixel's cell c = (y mod 128) * 128 + (x mod 128), instead of the hash.
  *   seed_pj  = H(H(seed + 2j) ^ p),  delta_pj = H(H(seed + 2j + 1) ^ p), where H is the
  *   integer hash "pcg" of Jarzynski and Olano (JCGT 2020):
  *   t = v*747796405 + 2891336453; w = ((t >> ((t >> 28) + 4)) ^ t) * 277803737; H = (w >> 22) ^ w.
@@ -270,6 +273,7 @@ qmc_status qmc_generate_lattice64(qmc_context ctx, qmc_stream stream,
 #define QMC_PIXEL_RANDOM_GENERATOR 16u  /* LATTICE: per-pixel random generator vector (Alg. 4) */
 #define QMC_PIXEL_HILBERT_SHIFT 32u     /* LATTICE: Hilbert-curve shift of phi_2 (Eq. PixelShiftedR1LS) */
 #define QMC_LATTICE_INSTANCES4 64u      /* LATTICE with QMC_PIXEL_RANDOM_GENERATOR: four instances */
+#define QMC_PIXEL_TABLE_SHIFT 256u      /* SOBOL/LATTICE with QMC_PIXEL_SHIFT: rotations from shift_table */
 
 #define QMC_F_GENZ 1u
 #define QMC_F_LOBES 2u
@@ -287,8 +291,10 @@ typedef struct {
     uint32_t flags;          /* QMC_PIXEL_NUS | QMC_PIXEL_SHIFT | QMC_SHIFT_XOR | QMC_LATTICE_BACKWARD  */
                              /* | QMC_PIXEL_RANDOM_GENERATOR | QMC_LATTICE_INSTANCES4                  */
                              /* | QMC_PIXEL_HILBERT_SHIFT (the last three: LATTICE only)              */
+                             /* | QMC_PIXEL_TABLE_SHIFT (with QMC_PIXEL_SHIFT)                        */
     const uint32_t* xor_scramble; /* XOR_TABLE: device u32 [s][16384] digit scrambles s_cj         */
     const uint32_t* xor_reorder;  /* XOR_TABLE: device u32 [16384] index reorderings r_c           */
+    const uint32_t* shift_table;  /* QMC_PIXEL_TABLE_SHIFT: device u32 [2][16384] rotation vectors  */
 } qmc_sampler;
 
 typedef struct {
@@ -315,7 +321,8 @@ qmc_status qmc_workspace_size(qmc_context ctx, const qmc_sampler* sampler, const
  *   counts: device u32 [width*height];  sums, means: device float32 [width*height];
  *   workspace: device, >= qmc_workspace_size(..., 0) bytes, no initial contents required.
  * Errors: INVALID_ARGUMENT (NULLs, sums and means both NULL, d > s, bad flags, begin > end,
- *         XOR_TABLE without its tables or with N not a power of two in [1, 2^32]),
+ *         XOR_TABLE without its tables or with N not a power of two in [1, 2^32],
+ *         QMC_PIXEL_TABLE_SHIFT without QMC_PIXEL_SHIFT or without shift_table),
  *         UNSUPPORTED (d not supported for the kind), WORKSPACE (too small). */
 qmc_status qmc_integrate_pixels(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
                                 const qmc_integrand* integrand, uint32_t width, uint32_t height,

@@ -23,6 +23,7 @@ from ._lib import (  # noqa: F401
     QMC_MAX_DEGREE,
     QMC_MAX_DIMS,
     QMC_PIXEL_HILBERT_SHIFT,
+    QMC_PIXEL_TABLE_SHIFT,
     QMC_PIXEL_NUS,
     QMC_PIXEL_RANDOM_GENERATOR,
     QMC_PIXEL_SHIFT,
@@ -272,10 +273,10 @@ class PixelSampler:
     """A qmc_sampler plus the device tensors it points to (kept alive with it)."""
 
     def __init__(self, kind, table, seed=0, flags=0, points_ld=0, offsets=None, s=None, xor_scramble=None,
-                 xor_reorder=None):
+                 xor_reorder=None, shift_table=None):
         self.table = table
         self.offsets = offsets
-        self.xor_scramble, self.xor_reorder = xor_scramble, xor_reorder
+        self.xor_scramble, self.xor_reorder, self.shift_table = xor_scramble, xor_reorder, shift_table
         self.kind = kind
         self.seed = seed
         self.flags = flags
@@ -284,17 +285,28 @@ class PixelSampler:
         self.s = s
         opt = lambda t, name: _dev_ptr(t, name).value if t is not None else None
         self.c = Sampler(kind, s, _dev_ptr(table, "table").value, points_ld, opt(offsets, "offsets"),
-                         seed & 0xFFFFFFFF, flags, opt(xor_scramble, "xor_scramble"), opt(xor_reorder, "xor_reorder"))
+                         seed & 0xFFFFFFFF, flags, opt(xor_scramble, "xor_scramble"), opt(xor_reorder, "xor_reorder"),
+                         opt(shift_table, "shift_table"))
+
+    @staticmethod
+    def _table_flags(flags, shift_table):
+        if shift_table is None:
+            return flags
+        if tuple(shift_table.shape) != (2, QMC_XOR_TABLE_CELLS):
+            raise ValueError("shift_table must be [2][16384]")
+        return flags | QMC_PIXEL_SHIFT | QMC_PIXEL_TABLE_SHIFT
 
     @classmethod
-    def sobol(cls, matrices, seed, flags=QMC_PIXEL_NUS | QMC_PIXEL_SHIFT):
+    def sobol(cls, matrices, seed, flags=QMC_PIXEL_NUS | QMC_PIXEL_SHIFT, shift_table=None):
+        """shift_table: optional u32 [2][16384] per-pixel rotations (Sec. 2.6.1) replacing the hashed ones."""
         if matrices.numel() != matrices.shape[0] * 32:
             raise ValueError("matrices must have shape [s][32]")
-        return cls(QMC_SAMPLER_SOBOL, matrices, seed, flags)
+        return cls(QMC_SAMPLER_SOBOL, matrices, seed, cls._table_flags(flags, shift_table), shift_table=shift_table)
 
     @classmethod
-    def lattice(cls, generator, seed, flags=QMC_PIXEL_SHIFT):
-        return cls(QMC_SAMPLER_LATTICE, generator, seed, flags)
+    def lattice(cls, generator, seed, flags=QMC_PIXEL_SHIFT, shift_table=None):
+        return cls(QMC_SAMPLER_LATTICE, generator, seed, cls._table_flags(flags, shift_table),
+                   shift_table=shift_table)
 
     @classmethod
     def xor_table(cls, points, scramble, reorder):

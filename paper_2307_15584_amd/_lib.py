@@ -33,6 +33,7 @@ QMC_SAMPLER_SOBOL = 1
 QMC_SAMPLER_LATTICE = 2
 QMC_SAMPLER_POINTS = 3
 QMC_SAMPLER_XOR_TABLE = 4
+QMC_PIXEL_TABLE_SHIFT = 256
 QMC_XOR_TABLE_CELLS = 16384
 QMC_F_GENZ = 1
 QMC_F_LOBES = 2
@@ -42,7 +43,8 @@ class Sampler(ctypes.Structure):
     """Mirror of qmc_sampler."""
     _fields_ = [("kind", ctypes.c_uint32), ("s", ctypes.c_uint32), ("table", ctypes.c_void_p),
                 ("points_ld", ctypes.c_uint64), ("offsets", ctypes.c_void_p), ("seed", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32), ("xor_scramble", ctypes.c_void_p), ("xor_reorder", ctypes.c_void_p)]
+                ("flags", ctypes.c_uint32), ("xor_scramble", ctypes.c_void_p), ("xor_reorder", ctypes.c_void_p),
+                ("shift_table", ctypes.c_void_p)]
 
 
 class Integrand(ctypes.Structure):

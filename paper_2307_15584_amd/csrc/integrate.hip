@@ -61,6 +61,8 @@ struct Args {
     const uint32_t* xor_scramble;
     const uint32_t* xor_reorder;
     uint32_t xor_mask;
+    // rotations from a 128 x 128 table of two-dimensional shifts [2][cells] (Sec. 2.6.1), or NULL
+    const uint32_t* shift_table;
     // integrand
     uint32_t fkind, d, L, pixel_seed;
     const float* params;        // theta (lobes)
@@ -345,6 +347,19 @@ __device__ __forceinline__ uint32_t pixel_hilbert_shift(const Args& a, uint32_t 
     return radical_inverse3_u32(hilbert_index(x, y, a.hilbert_order));
 }
 
+// Cell of pixel p in the 128 x 128 tables of Sec. 2.6.1: (y mod 128) * 128 + (x mod 128).
+__device__ __forceinline__ uint32_t pixel_cell(const Args& a, uint32_t p) {
+    const uint32_t y = p / a.width, x = p - y * a.width;
+    return ((y & 127u) << 7) | (x & 127u);
+}
+
+// Rotation of component j of pixel p: the hashed per-pixel value, or the pixel's entry of the
+// table of two-dimensional shifts, shared by every pair of dimensions (entry j mod 2).
+__device__ __forceinline__ uint32_t pixel_rotation(const Args& a, uint32_t kc_j, uint32_t j, uint32_t p) {
+    if (a.shift_table) return a.shift_table[(j & 1u) * QMC_XOR_TABLE_CELLS + pixel_cell(a, p)];
+    return dev::pcg_hash(kc_j ^ p);
+}
+
 // Per-pixel random generator component (Alg. 4): H(k + c) | 1 with k = H(H(seed + 2j) ^ p).
 __device__ __forceinline__ uint32_t pixel_generator(uint32_t kn_j, uint32_t p, uint32_t c) {
     return dev::pcg_hash(dev::pcg_hash(kn_j ^ p) + c) | 1u;
@@ -364,8 +379,7 @@ __device__ __forceinline__ void sample_point(float (&x)[kGen<D>], const SamplerL
     constexpr int G = kGen<D>;
     if constexpr (SK == QMC_SAMPLER_XOR_TABLE) {
         // the pixel's cell of the 128 x 128 tables; stored point (i ^ r_c) mod N, digits ^ s_cj
-        const uint32_t y = p / a.width, xc = p - y * a.width;
-        const uint32_t c = ((y & 127u) << 7) | (xc & 127u);
+        const uint32_t c = pixel_cell(a, p);
         const uint32_t idx = valid ? ((i ^ a.xor_reorder[c]) & a.xor_mask) : 0u;
 #pragma unroll
         for (int jj = 0; jj < G; ++jj) {
@@ -417,7 +431,7 @@ __device__ __forceinline__ void sample_point(float (&x)[kGen<D>], const SamplerL
                     v = dev::nus_from_mirrored(v, sd, sm);
                 }
                 if constexpr (SHIFT) {
-                    const uint32_t sh = PX ? PX->shift[j] : PK ? PK->shift[j][q] : dev::pcg_hash(S.kc[j] ^ p);
+                    const uint32_t sh = PX ? PX->shift[j] : PK ? PK->shift[j][q] : pixel_rotation(a, S.kc[j], j, p);
                     v = a.sxor ? (v ^ sh) : (v + sh);
                 }
                 x[jj] = dev::u32_to_unifloat(v);
@@ -474,7 +488,7 @@ __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S,
                 PX.seed[lane] = sd;
                 PX.sm[lane] = dev::seed_multiplier(sd);
             }
-            if constexpr (SHIFT) PX.shift[lane] = dev::pcg_hash(S.kc[lane] ^ pp);
+            if constexpr (SHIFT) PX.shift[lane] = pixel_rotation(a, S.kc[lane], lane, pp);
             if constexpr (DELTA) PX.delta[lane] = pixel_delta(S.kd[lane], pp);
             if constexpr (SK == QMC_SAMPLER_SOBOL) PX.B[lane] = S.B0[lane];
             if constexpr (SK == QMC_SAMPLER_LATTICE) {
@@ -531,7 +545,7 @@ __device__ __forceinline__ void walk_tile(const Args& a, const SamplerLds<D>& S,
         // every lane hashes its own pixel's values (pixels without packed samples are unused)
         for (uint32_t j = 0; j < a.d && j < D; ++j) {
             if constexpr (NUS) PK->seed[j][lane] = dev::pcg_hash(S.kn[j] ^ (p0 + lane));
-            if constexpr (SHIFT) PK->shift[j][lane] = dev::pcg_hash(S.kc[j] ^ (p0 + lane));
+            if constexpr (SHIFT) PK->shift[j][lane] = pixel_rotation(a, S.kc[j], j, p0 + lane);
         }
         if constexpr (SK == QMC_SAMPLER_LATTICE) {
             if (a.lhilbert) PK->hshift[lane] = hs_own;
@@ -1282,13 +1296,16 @@ qmc_status validate_sampler(const char* who, const qmc_sampler* sp, uint32_t d) 
     if (!sp->table) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: sampler table is NULL", who);
     if (sp->s == 0 || sp->s > QMC_MAX_DIMS) return fail(QMC_ERR_OUT_OF_RANGE, "%s: sampler s out of range", who);
     const uint32_t lattice_only = QMC_PIXEL_RANDOM_GENERATOR | QMC_LATTICE_INSTANCES4 | QMC_PIXEL_HILBERT_SHIFT;
-    const uint32_t allowed = QMC_PIXEL_NUS | QMC_PIXEL_SHIFT | QMC_SHIFT_XOR | QMC_LATTICE_BACKWARD | lattice_only;
+    const uint32_t allowed =
+        QMC_PIXEL_NUS | QMC_PIXEL_SHIFT | QMC_SHIFT_XOR | QMC_LATTICE_BACKWARD | QMC_PIXEL_TABLE_SHIFT | lattice_only;
     if (sp->flags & ~allowed) return fail(QMC_ERR_INVALID_ARGUMENT, "%s: unknown sampler flags", who);
     if (sp->kind != QMC_SAMPLER_SOBOL && (sp->flags & QMC_PIXEL_NUS))
         return fail(QMC_ERR_INVALID_ARGUMENT, "%s: only the Sobol' sampler has a nested scramble", who);
     if (sp->kind != QMC_SAMPLER_LATTICE && (sp->flags & lattice_only))
         return fail(QMC_ERR_INVALID_ARGUMENT, "%s: generator and Hilbert-shift options are for the lattice sampler",
                     who);
+    if ((sp->flags & QMC_PIXEL_TABLE_SHIFT) && (!(sp->flags & QMC_PIXEL_SHIFT) || !sp->shift_table))
+        return fail(QMC_ERR_INVALID_ARGUMENT, "%s: table rotations need QMC_PIXEL_SHIFT and a shift table", who);
     if ((sp->flags & QMC_LATTICE_INSTANCES4) && !(sp->flags & QMC_PIXEL_RANDOM_GENERATOR))
         return fail(QMC_ERR_INVALID_ARGUMENT, "%s: four instances need per-pixel random generators", who);
     if (sp->kind == QMC_SAMPLER_POINTS && !sp->offsets)
@@ -1430,6 +1447,7 @@ Args base_args(const qmc_sampler* sp, uint32_t d, uint32_t W, uint32_t H, const 
     a.xor_scramble = sp->xor_scramble;
     a.xor_reorder = sp->xor_reorder;
     a.xor_mask = static_cast<uint32_t>(sp->points_ld - 1);
+    a.shift_table = (sp->flags & QMC_PIXEL_TABLE_SHIFT) ? sp->shift_table : nullptr;
     a.d = d;
     a.num_pixels = P;
     a.counts = counts;

@@ -239,6 +239,7 @@ extern "C" qmc_status qmc_integrate_progressive(qmc_context ctx, qmc_stream stre
         sampler->kind, sampler->s, reinterpret_cast<uint64_t>(sampler->table), sampler->points_ld,
         reinterpret_cast<uint64_t>(sampler->offsets), sampler->seed, sampler->flags,
         reinterpret_cast<uint64_t>(sampler->xor_scramble), reinterpret_cast<uint64_t>(sampler->xor_reorder),
+        reinterpret_cast<uint64_t>(sampler->shift_table),
         integrand->kind, integrand->d,
         integrand->num_lobes, integrand->pixel_seed, reinterpret_cast<uint64_t>(integrand->params),
         reinterpret_cast<uint64_t>(integrand->pixel_params), width, height, reinterpret_cast<uint64_t>(counts),

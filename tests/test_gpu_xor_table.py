@@ -1,14 +1,16 @@
-"""GPU parity of the table-driven per-pixel XOR sampler (Sec. 2.6.1): materialised samples bit
-for bit against the oracle, the fused forward, adjoint and L2 step against FP64, a 1920x1080
-frame at sampled pixels, and argument errors.  Images wider or taller than 128 pixels make the
-tables repeat; sample counts above N make the stored points repeat; reorder entries span all
-32 bits, so the index is reduced modulo N."""
+"""GPU parity of the table-driven per-pixel samplers of Sec. 2.6.1.  The XOR sampler:
+materialised samples bit for bit against the oracle, the fused forward, adjoint and L2 step
+against FP64, a 1920x1080 frame at sampled pixels, and argument errors.  Images wider or taller
+than 128 pixels make the tables repeat; sample counts above N make the stored points repeat;
+reorder entries span all 32 bits, so the index is reduced modulo N.  The table of
+two-dimensional rotations: the same checks for lattice and Sobol' samplers."""
 
 import numpy as np
 import pytest
 
 from oracle import digital, estimator, scramble
-from synth import counts_uniform, genz_params, lobe_params, nus_seeds, perturb, pick, sobol_direction_init, u32_draws
+from synth import (counts_uniform, genz_params, lattice_vector, lobe_params, nus_seeds, perturb, pick,
+                   sobol_direction_init, u32_draws)
 
 pytestmark = pytest.mark.gpu
 
@@ -179,3 +181,88 @@ def test_argument_errors(qmc):
     ok = qmc.qmc_integrate_pixels(qmc.PixelSampler.xor_table(pts, scr, reo), ig, 4, 4, dc)
     torch.cuda.synchronize()
     assert ok.shape == (16,)
+
+
+NUS, SHIFT, XOR, BACK = 4, 8, 1, 2
+
+
+def _rot_pair(q, kind, s, W, H, flags, seed):
+    table = u32_draws(seed, 2 * CELLS).reshape(2, CELLS)
+    if kind == "lattice":
+        g = lattice_vector(s, 30, 3)
+        dev = q.PixelSampler.lattice(q.from_u32(g), 0x51, flags, shift_table=q.from_u32(table))
+    else:
+        g = digital.sobol_matrices(s, sobol_direction_init(s, 0))
+        dev = q.PixelSampler.sobol(q.from_u32(g), 0x51, flags, shift_table=q.from_u32(table))
+    ora = {"kind": kind, "s": s, "table": g, "seed": 0x51, "width": W, "height": H, "shift_table": table,
+           "flags": flags | SHIFT | estimator.PIXEL_TABLE_SHIFT}
+    return dev, ora
+
+
+ROT_CASES = [
+    # kind, flags, W, H, d
+    ("lattice", SHIFT, 131, 3, 8),
+    ("lattice", SHIFT | XOR | BACK, 5, 130, 40),
+    ("sobol", NUS | SHIFT, 131, 3, 8),
+    ("sobol", SHIFT | XOR, 4, 131, 3),
+]
+
+
+@pytest.mark.parametrize("case", ROT_CASES, ids=[str(c) for c in ROT_CASES])
+def test_table_rotations_materialised_bit_exact(qmc, case):
+    import torch
+
+    kind, flags, W, H, d = case
+    counts = _counts_edge(W * H)
+    ds, os_ = _rot_pair(qmc, kind, d, W, H, flags, 70)
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    offs = qmc.qmc_sample_offsets(dc)
+    pts = qmc.qmc_generate_pixel_samples(ds, d, W, H, dc, offs, int(counts.astype(np.int64).sum()))
+    torch.cuda.synchronize()
+    p_arr, i_arr = _all_pairs(counts)
+    want = estimator.pixel_samples_f32(os_, p_arr, i_arr)
+    assert np.array_equal(pts.cpu().numpy().view(np.uint32), want.view(np.uint32))
+
+
+@pytest.mark.parametrize("kind,flags", [("lattice", SHIFT), ("sobol", NUS | SHIFT)])
+def test_table_rotations_fused_genz_and_adjoint(qmc, kind, flags):
+    import torch
+
+    W, H = 131, 4
+    P = W * H
+    counts = _counts_edge(P)
+    ds, os_ = _rot_pair(qmc, kind, 8, W, H, flags, 71)
+    pp = genz_params(P, 4)
+    got = _genz(qmc, ds, W, H, counts, pp)
+    ref = estimator.integrate_pixels(os_, {"kind": "genz", "d": 8, "pixel_params": pp}, counts, range(P))
+    assert _est_tol(got, ref).all()
+    L, d = 64, 8
+    theta = lobe_params(L, d, 6)
+    ig = qmc.PixelIntegrand.lobes(torch.from_numpy(theta).cuda(), L, d, 9)
+    oig = {"kind": "lobes", "d": d, "num_lobes": L, "params": theta, "pixel_seed": 9}
+    target = estimator.integrate_pixels(os_, dict(oig, params=perturb(theta, 7)), counts, range(P))["mean"]
+    _, g64, means64 = estimator.loss_and_gradient(os_, oig, counts, range(P), target)
+    gm = (2.0 * (means64 - target) / P).astype(np.float32)
+    g = qmc.qmc_integrate_pixels_backward(ds, ig, W, H, torch.from_numpy(counts.view(np.int32)).cuda(),
+                                          torch.from_numpy(gm).cuda())
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    ok = np.abs(g - g64) <= 1e-4 * np.maximum(np.abs(g64), 1e-3 * np.max(np.abs(g64)))
+    assert ok.all(), (np.nonzero(~ok)[0][:10], g[~ok][:5], g64[~ok][:5])
+
+
+def test_table_rotation_argument_errors(qmc):
+    import torch
+
+    g = qmc.from_u32(lattice_vector(8, 30, 3))
+    table = qmc.from_u32(u32_draws(72, 2 * CELLS).reshape(2, CELLS))
+    ig = qmc.PixelIntegrand.genz(torch.from_numpy(genz_params(16, 4)).cuda())
+    dc = torch.full((16,), 8, dtype=torch.int32, device="cuda")
+    L, T = qmc.QMC_SAMPLER_LATTICE, qmc.QMC_PIXEL_TABLE_SHIFT
+    for smp in (qmc.PixelSampler(L, g, 1, T, shift_table=table),          # without QMC_PIXEL_SHIFT
+                qmc.PixelSampler(L, g, 1, T | SHIFT)):                     # without the table
+        with pytest.raises(qmc.QMCError) as e:
+            qmc.qmc_integrate_pixels(smp, ig, 4, 4, dc)
+        assert e.value.status == 1
+    with pytest.raises(ValueError):
+        qmc.PixelSampler.lattice(g, 1, shift_table=table[:, :100].contiguous())
