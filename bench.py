@@ -12,7 +12,7 @@ The same line carries the per-pixel integration workloads ("pixels"): the fused 
 (generate + evaluate + reduce in one launch, and the adjoint that recomputes samples) timed
 next to the plain path (materialise the per-pixel samples in HBM, then integrate them):
   * Genz, 1920x1080 pixels, 2^k samples per pixel (k in 0..8 from a smooth map), d = 8, also
-    under the lattice samplers of Sec. 3 and the table-driven XOR sampler of Sec. 2.6.1;
+    under the lattice samplers of Sec. 3 and the table-driven samplers of Sec. 2.6.1;
   * Gaussian lobes, 1920x1080 x 64 spp, d = 8, 64 lobes: forward + L2-loss gradient +
     adjoint ("fwd+bwd").
   * the 3840x2160 progressive run: 16 graph-captured passes of 64 spp, d = 64, 32 lobes,
@@ -272,6 +272,12 @@ def pixel_workloads(torch, q, reps, progressive):
     ms = _timed(torch, lambda: q.qmc_integrate_pixels(xs, ig3, W, H, dc3, means=means, workspace=ws3), reps)
     out["genz_1920x1080_uneven"]["xor_table_sampler"] = {
         "stored_points": 4096, "fused_ms": round(ms, 4), "fused_pixel_samples_per_s": round(n3 / (ms * 1e-3), 1)}
+    # the lattice rotated per pixel from one 128 x 128 table of two-dimensional shifts (Sec. 2.6.1)
+    smp = q.PixelSampler.lattice(gl, 0xC3, q.QMC_PIXEL_SHIFT,
+                                 shift_table=q.from_u32(u32_draws(23, 2 * q.QMC_XOR_TABLE_CELLS).reshape(2, -1)))
+    ms = _timed(torch, lambda: q.qmc_integrate_pixels(smp, ig3, W, H, dc3, means=means, workspace=ws3), reps)
+    out["genz_1920x1080_uneven"]["lattice_table_rotations"] = {
+        "fused_ms": round(ms, 4), "fused_pixel_samples_per_s": round(n3 / (ms * 1e-3), 1)}
     del pts3
 
     # Gaussian lobes, forward + L2 gradient + adjoint

@@ -408,7 +408,8 @@ qmc_status qmc_autotune_generate(qmc_context ctx, qmc_stream stream, uint32_t ki
 
 /* Times the integration launch shapes (persistent grid of 4..32 wavefronts per compute unit,
  * static or atomic-queue schedule) for this problem and keeps the fastest in the context for
- * (integrand kind, d, direction).  Forward candidates write means into scratch (device
+ * (integrand kind, d, direction); among shapes within 1 % of the fastest, the one with the
+ * fewest wavefronts per compute unit.  Forward candidates write means into scratch (device
  * float32 [P]); backward candidates (backward != 0, grad_means required) add gradients into
  * scratch (device float32 [n_theta]).  Synchronises `stream`.  report as above. */
 qmc_status qmc_autotune_integrate(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
