@@ -117,3 +117,32 @@ def test_header_constants_match_the_binding():
     for name in ("QMC_PIXEL_NUS", "QMC_PIXEL_SHIFT", "QMC_PIXEL_RANDOM_GENERATOR", "QMC_PIXEL_HILBERT_SHIFT",
                  "QMC_LATTICE_INSTANCES4", "QMC_SHIFT_XOR", "QMC_LATTICE_BACKWARD"):
         assert hasattr(_lib, name), name
+
+
+def test_struct_mirrors_match_the_header(tmp_path):
+    """The binding's ctypes structs have the C structs' size and field offsets (compiled with gcc
+    against include/qmc.h)."""
+    import shutil
+    import subprocess
+
+    from paper_2307_15584_amd import _lib
+
+    if not shutil.which("gcc"):
+        pytest.skip("no host C compiler")
+    mirrors = {"qmc_sampler": _lib.Sampler, "qmc_integrand": _lib.Integrand}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "qmc.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
