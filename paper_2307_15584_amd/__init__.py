@@ -283,10 +283,13 @@ class PixelSampler:
         if s is None:
             s = table.shape[0]
         self.s = s
-        opt = lambda t, name: _dev_ptr(t, name).value if t is not None else None
-        self.c = Sampler(kind, s, _dev_ptr(table, "table").value, points_ld, opt(offsets, "offsets"),
-                         seed & 0xFFFFFFFF, flags, opt(xor_scramble, "xor_scramble"), opt(xor_reorder, "xor_reorder"),
-                         opt(shift_table, "shift_table"))
+        torch = _torch()
+        opt = lambda t, name, types=None: _dev_ptr(t, name, types).value if t is not None else None
+        u32 = _u32_types()
+        tab_types = (torch.float32,) if kind == QMC_SAMPLER_POINTS else u32
+        self.c = Sampler(kind, s, _dev_ptr(table, "table", tab_types).value, points_ld, opt(offsets, "offsets"),
+                         seed & 0xFFFFFFFF, flags, opt(xor_scramble, "xor_scramble", u32),
+                         opt(xor_reorder, "xor_reorder", u32), opt(shift_table, "shift_table", u32))
 
     @staticmethod
     def _table_flags(flags, shift_table):

@@ -266,6 +266,10 @@ def test_table_rotation_argument_errors(qmc):
         assert e.value.status == 1
     with pytest.raises(ValueError):
         qmc.PixelSampler.lattice(g, 1, shift_table=table[:, :100].contiguous())
+    with pytest.raises(TypeError):
+        qmc.PixelSampler.lattice(g, 1, shift_table=table.float())
+    with pytest.raises(TypeError):
+        qmc.PixelSampler.lattice(g.float(), 1)
 
 
 def test_progressive_graph_with_table_samplers(qmc):
