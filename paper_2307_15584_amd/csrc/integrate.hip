@@ -369,7 +369,7 @@ __device__ __forceinline__ uint32_t pixel_generator(uint32_t kn_j, uint32_t p, u
 //   base:   per-round index part in LDS (PixelLds::B or SamplerLds::B0); with it, the Sobol'
 //           index part is base[j] ^ T[j][k] for k = i - begin mod 64.  NULL: C_j i directly.
 //   PX:     per-pixel values of a big pixel; else PK: the tile's per-pixel values, pixel q;
-//           both NULL: derive them from the hash per lane;
+//           both NULL: derive them per lane (hash, or the rotation table of Sec. 2.6.1);
 //   valid:  false for lanes past the end of a window, which must not read materialised samples.
 template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK>
 __device__ __forceinline__ void sample_point(float (&x)[kGen<D>], const SamplerLds<D>& S, const PixelLds<D>* PX,
