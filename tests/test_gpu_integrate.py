@@ -311,11 +311,13 @@ def test_full_size_lobes_forward_sampled_pixels(qmc):
     assert _est_tol(got[pix], ref).all()
 
 
-def test_full_size_progressive_sampled_pixels(qmc):
+@pytest.mark.parametrize("kind,flags", [("sobol", NUS | SHIFT), ("lattice", SHIFT)])
+def test_full_size_progressive_sampled_pixels(qmc, kind, flags):
     """The 3840x2160 progressive workload as timed: 16 graph-replayed passes of 64 spp, counts
-    64..1024, 32 lobes in 64 dims, NUS + shift.  Means at 300 sampled pixels vs FP64; then the
-    adjoint over the whole frame with dL/dI nonzero only at 48 sampled pixels vs the FP64
-    gradient of those pixels, within 1e-4 relative or 2e-5 of the size of the terms summed."""
+    64..1024, 32 lobes in 64 dims, Sobol' (NUS + shift) or lattice (shift) samples.  Means at 300
+    sampled pixels vs FP64; then (Sobol') the adjoint over the whole frame with dL/dI nonzero
+    only at 48 sampled pixels vs the FP64 gradient of those pixels, within 1e-4 relative or 2e-5
+    of the size of the terms summed."""
     import torch
 
     from synth import counts_progressive
@@ -324,7 +326,7 @@ def test_full_size_progressive_sampled_pixels(qmc):
     P = W * H
     counts = counts_progressive(W, H, 5, passes=16, spp_per_pass=64)
     theta, dtheta = _lobes_setup(qmc, L, d)
-    ds, os_ = _sampler_pair(qmc, "sobol", 64, 0xC5, NUS | SHIFT)
+    ds, os_ = _sampler_pair(qmc, kind, 64, 0xC5, flags)
     ig = qmc.PixelIntegrand.lobes(dtheta, L, d, 9)
     oig = {"kind": "lobes", "d": d, "num_lobes": L, "params": theta, "pixel_seed": 9}
     dc = torch.from_numpy(counts.view(np.int32)).cuda()
@@ -338,6 +340,8 @@ def test_full_size_progressive_sampled_pixels(qmc):
     ok = _est_tol(got, ref)
     assert ok.all(), (pix[~ok][:10], got[~ok][:5], ref["mean"][~ok][:5])
     del sums, means
+    if kind != "sobol":
+        return
 
     gpix = pick(P, 48, 45)
     gvals = (np.random.default_rng(46).uniform(-1.0, 1.0, gpix.size) / gpix.size).astype(np.float32)
