@@ -227,12 +227,12 @@ qmc_status qmc_generate_lattice64(qmc_context ctx, qmc_stream stream,
  *            unless QMC_PIXEL_RANDOM_GENERATOR (below);
  *   then v = v + delta_pj mod 2^32 with QMC_PIXEL_SHIFT (v ^ delta_pj with QMC_SHIFT_XOR),
  *   and x = map_u32_to_unifloat(v).
- *   QMC_PIXEL_TABLE_SHIFT (with QMC_PIXEL_SHIFT; Sec. 2.6.1, one table of two-dimensional
- *     rotations repeated for all pairs of dimensions): delta_pj = shift_table[(j mod 2) *
- *     16384 + c] for the pixel's cell c = (y mod 128) * 128 + (x mod 128), instead of the hash.
  *   seed_pj  = H(H(seed + 2j) ^ p),  delta_pj = H(H(seed + 2j + 1) ^ p), where H is the
  *   integer hash "pcg" of Jarzynski and Olano (JCGT 2020):
  *   t = v*747796405 + 2891336453; w = ((t >> ((t >> 28) + 4)) ^ t) * 277803737; H = (w >> 22) ^ w.
+ *   QMC_PIXEL_TABLE_SHIFT (with QMC_PIXEL_SHIFT; Sec. 2.6.1, one table of two-dimensional
+ *     rotations repeated for all pairs of dimensions): delta_pj = shift_table[(j mod 2) *
+ *     16384 + c] for the pixel's cell c = (y mod 128) * 128 + (x mod 128), instead of the hash.
  * Lattice options of Sec. 3:
  *   QMC_PIXEL_RANDOM_GENERATOR (Alg. 4): pixel p's own generator, g_pj = H(H(H(seed + 2j) ^ p)
  *     + c) | 1 for instance c = 0 (the table is still read but its values are not used);
