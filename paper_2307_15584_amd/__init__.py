@@ -324,7 +324,13 @@ class PixelSampler:
 
     @classmethod
     def points(cls, samples, offsets):
-        """Materialised samples [d][ld] float32 with per-pixel offsets (int64 [P+1])."""
+        """Materialised samples [d][ld] float32 with per-pixel offsets (int64 [P+1]); sample i of
+        pixel p is column offsets[p] + i, so offsets[P] must not exceed ld."""
+        torch = _torch()
+        if samples.dim() != 2 or samples.dtype != torch.float32:
+            raise TypeError("samples must be a float32 tensor [d][ld]")
+        if offsets.dim() != 1 or offsets.dtype != torch.int64:
+            raise TypeError("offsets must be an int64 vector [P+1]")
         return cls(QMC_SAMPLER_POINTS, samples, 0, 0, points_ld=samples.shape[1], offsets=offsets,
                    s=samples.shape[0])
 
@@ -369,9 +375,11 @@ def _workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
-def _check_counts(counts, P):
+def _check_counts(counts, P, sampler=None):
     if counts.numel() != P:
         raise ValueError("counts must have width*height entries")
+    if sampler is not None and sampler.kind == QMC_SAMPLER_POINTS and sampler.offsets.numel() != P + 1:
+        raise ValueError("the POINTS sampler's offsets must have width*height + 1 entries")
 
 
 def qmc_integrate_pixels(sampler, integrand, width, height, counts, sample_begin=0, sample_end=0xFFFFFFFF,
@@ -379,7 +387,7 @@ def qmc_integrate_pixels(sampler, integrand, width, height, counts, sample_begin
     """Per-pixel estimates; returns means (allocated when neither sums nor means is given)."""
     torch = _torch()
     P = width * height
-    _check_counts(counts, P)
+    _check_counts(counts, P, sampler)
     if sums is None and means is None:
         means = torch.empty(P, dtype=torch.float32, device=counts.device)
     for t, nm in ((sums, "sums"), (means, "means")):
@@ -400,7 +408,7 @@ def qmc_integrate_pixels_backward(sampler, integrand, width, height, counts, gra
     """Adds dL/dtheta into grad_params (zeros if not given); returns grad_params."""
     torch = _torch()
     P = width * height
-    _check_counts(counts, P)
+    _check_counts(counts, P, sampler)
     if grad_means.numel() != P:
         raise ValueError("grad_means must have width*height entries")
     if grad_params is None:
@@ -421,7 +429,7 @@ def qmc_integrate_pixels_l2_step(sampler, integrand, width, height, counts, targ
     loss and grad_params are added into (zeros when not given)."""
     torch = _torch()
     P = width * height
-    _check_counts(counts, P)
+    _check_counts(counts, P, sampler)
     if target.numel() != P:
         raise ValueError("target must have width*height entries")
     if means is None:
@@ -452,11 +460,22 @@ def qmc_sample_offsets(counts):
 
 
 def qmc_generate_pixel_samples(sampler, d, width, height, counts, offsets, total, out=None):
-    """Materialised samples float32 [d][total] (the plain path's generation step)."""
+    """Materialised samples float32 [d][total] (the plain path's generation step).
+
+    offsets: int64 [P+1], the exclusive prefix sums of counts (qmc_sample_offsets), whose last
+    entry is `total`; out: float32 [>= d][>= total].  The kernel writes column offsets[p] + i
+    for sample i of pixel p, so these shapes bound every store."""
     torch = _torch()
-    _check_counts(counts, width * height)
+    P = width * height
+    _check_counts(counts, P)
+    if not isinstance(offsets, torch.Tensor) or offsets.dtype != torch.int64 or offsets.numel() != P + 1:
+        raise TypeError("offsets must be an int64 tensor of width*height + 1 entries")
     if out is None:
         out = torch.empty((d, max(int(total), 1)), dtype=torch.float32, device=counts.device)
+    if out.dtype != torch.float32 or out.dim() != 2:
+        raise TypeError("out must be a float32 tensor [d][ld]")
+    if out.shape[0] < d or out.shape[1] < total:
+        raise ValueError("out has shape %s; [>= %d][>= %d] needed" % (tuple(out.shape), d, total))
     ws = _workspace(256, counts.device)
     check(load().qmc_generate_pixel_samples(
         context(counts.device), _stream(), ctypes.byref(sampler.c), d, width, height,
@@ -470,7 +489,7 @@ def qmc_integrate_progressive(sampler, integrand, width, height, counts, passes,
     """passes x spp_per_pass windows added into sums (graph-captured and replayed when use_graph)."""
     torch = _torch()
     P = width * height
-    _check_counts(counts, P)
+    _check_counts(counts, P, sampler)
     if workspace is None:
         workspace = _workspace(qmc_workspace_size(sampler, integrand, width, height, False), counts.device)
     check(load().qmc_integrate_progressive(

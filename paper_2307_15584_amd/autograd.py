@@ -18,6 +18,7 @@ class QMCIntegrate(torch.autograd.Function):
         means = qmc_integrate_pixels(sampler, ig, width, height, counts)
         ctx.sampler, ctx.integrand, ctx.shape = sampler, ig, (width, height)
         ctx.save_for_backward(counts)
+        ctx.theta_shape = theta.shape
         return means
 
     @staticmethod
@@ -28,7 +29,7 @@ class QMCIntegrate(torch.autograd.Function):
         width, height = ctx.shape
         g = qmc_integrate_pixels_backward(ctx.sampler, ctx.integrand, width, height, counts,
                                           grad_means.contiguous().float())
-        return g, None, None, None, None, None
+        return g.view(ctx.theta_shape), None, None, None, None, None
 
 
 def integrate(theta, sampler, integrand, width, height, counts):

@@ -411,3 +411,143 @@ def test_fused_l2_step_matches_oracle(qmc, d, L, W, H, cname):
     ok = np.abs(g - g64) <= 1e-4 * np.maximum(np.abs(g64), 1e-3 * np.max(np.abs(g64)))
     assert ok.all(), (np.nonzero(~ok)[0][:10], g[~ok][:5], g64[~ok][:5])
     assert abs(float(loss.cpu()[0]) - loss64) <= 1e-4 * loss64
+
+
+def test_binding_rejects_bad_plain_path_buffers(qmc):
+    """The binding checks dtype and shape of every buffer the sample kernels index through
+    device-resident offsets, before any launch."""
+    import torch
+
+    W, H, d = 8, 4, 8
+    P = W * H
+    counts = _counts_edge(P)
+    ds, _ = _sampler_pair(qmc, "sobol", 8, 3, NUS | SHIFT)
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    offs = qmc.qmc_sample_offsets(dc)
+    total = int(counts.astype(np.int64).sum())
+    with pytest.raises(TypeError):   # int32 offsets
+        qmc.qmc_generate_pixel_samples(ds, d, W, H, dc, offs.to(torch.int32), total)
+    with pytest.raises(TypeError):   # offsets of the wrong length
+        qmc.qmc_generate_pixel_samples(ds, d, W, H, dc, offs[:-1], total)
+    with pytest.raises(TypeError):   # float64 output
+        qmc.qmc_generate_pixel_samples(ds, d, W, H, dc, offs, total,
+                                       out=torch.empty((d, total), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):  # too few rows
+        qmc.qmc_generate_pixel_samples(ds, d, W, H, dc, offs, total,
+                                       out=torch.empty((d - 1, total), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):  # too few columns
+        qmc.qmc_generate_pixel_samples(ds, d, W, H, dc, offs, total,
+                                       out=torch.empty((d, total - 1), dtype=torch.float32, device="cuda"))
+    pts = qmc.qmc_generate_pixel_samples(ds, d, W, H, dc, offs, total)
+    with pytest.raises(TypeError):
+        qmc.PixelSampler.points(pts, offs.to(torch.int32))
+    with pytest.raises(TypeError):
+        qmc.PixelSampler.points(pts.double(), offs)
+    ig = qmc.PixelIntegrand.genz(torch.from_numpy(genz_params(P, 4)).cuda())
+    short = qmc.PixelSampler.points(pts, offs[:-1])
+    with pytest.raises(ValueError):
+        qmc.qmc_integrate_pixels(short, ig, W, H, dc)
+    torch.cuda.synchronize()
+
+
+def test_autograd_keeps_the_shape_of_theta(qmc):
+    """A parameter tensor of any shape gets a gradient of its own shape (the kernels see the
+    flat [L (2d + 1)] layout)."""
+    import torch
+
+    W, H, d, L = 8, 8, 8, 4
+    counts = counts_uniform(W, H, 64)
+    theta, dtheta = _lobes_setup(qmc, L, d)
+    ds, _ = _sampler_pair(qmc, "sobol", 8, 21, NUS | SHIFT)
+    ig = qmc.PixelIntegrand.lobes(dtheta, L, d, 9)
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    th = dtheta.clone().view(L, 2 * d + 1).requires_grad_(True)
+    means = qmc.integrate(th, ds, ig, W, H, dc)
+    means.sum().backward()
+    assert th.grad.shape == th.shape
+    flat = dtheta.clone().requires_grad_(True)
+    qmc.integrate(flat, ds, ig, W, H, dc).sum().backward()
+    torch.cuda.synchronize()
+    assert torch.equal(th.grad.reshape(-1), flat.grad)
+
+
+def _confined_grad_ok(g, g64, size):
+    """The gradient tolerance: |g - g64| <= 1e-4 max(|g64|, 1e-3 max|g64|); components whose
+    summed term sizes exceed five times that scale (they cancel) may instead be within 2e-5 of
+    the size of the terms, the FP32 rounding bound of their sums."""
+    scale = np.maximum(np.abs(g64), 1e-3 * np.max(np.abs(g64)))
+    err = np.abs(g - g64)
+    return (err <= 1e-4 * scale) | ((size > 5 * scale) & (err <= 2e-5 * size))
+
+
+def _c4_setup(qmc):
+    """The 1920x1080 x 64 spp lobe workload (d = 8, 64 lobes), in the launch shape the benchmark
+    times (the autotuner's choice for the forward and the adjoint direction)."""
+    import torch
+
+    W, H, d, L = 1920, 1080, 8, 64
+    P = W * H
+    counts = counts_uniform(W, H, 64)
+    theta, dtheta = _lobes_setup(qmc, L, d)
+    ds, os_ = _sampler_pair(qmc, "sobol", 8, 0xC4, NUS | SHIFT)
+    ig = qmc.PixelIntegrand.lobes(dtheta, L, d, 9)
+    oig = {"kind": "lobes", "d": d, "num_lobes": L, "params": theta, "pixel_seed": 9}
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    qmc.qmc_autotune_integrate(ds, ig, W, H, dc)
+    qmc.qmc_autotune_integrate(ds, ig, W, H, dc, backward=True,
+                               grad_means=torch.full((P,), 1e-7, dtype=torch.float32, device="cuda"))
+    return W, H, P, counts, dc, ds, os_, ig, oig
+
+
+def test_full_size_lobes_adjoint_sampled_pixels(qmc):
+    """1920x1080 x 64 spp adjoint over the whole frame with dL/dI nonzero at 48 sampled pixels,
+    against the FP64 gradient of those pixels."""
+    import torch
+
+    W, H, P, counts, dc, ds, os_, ig, oig = _c4_setup(qmc)
+    gpix = pick(P, 48, 47)
+    gvals = (np.random.default_rng(48).uniform(-1.0, 1.0, gpix.size) / gpix.size).astype(np.float32)
+    gm = torch.zeros(P, dtype=torch.float32, device="cuda")
+    gm[torch.from_numpy(gpix).cuda()] = torch.from_numpy(gvals).cuda()
+    g = qmc.qmc_integrate_pixels_backward(ds, ig, W, H, dc, gm)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    g64 = estimator.lobes_gradient(os_, oig, counts, gpix, gvals)
+    size = estimator.lobes_gradient(os_, oig, counts, gpix, gvals, sizes=True)
+    ok = _confined_grad_ok(g, g64, size)
+    assert ok.all(), (np.nonzero(~ok)[0][:10], g[~ok][:5], g64[~ok][:5], size[~ok][:5])
+
+
+def test_full_size_fused_l2_step_sampled_pixels(qmc):
+    """The fused forward + L2 gradient + adjoint at 1920x1080 x 64 spp.  A first call gives the
+    means; the target is set to them except at 48 sampled pixels, so in a second call (bitwise
+    the same estimates) dL/dI_p = 2 (I_p - T_p) / P is exactly zero at every other pixel.  Means
+    at 400 sampled pixels against FP64, the loss and the gradient against the FP64 values of the
+    48 perturbed pixels."""
+    import torch
+
+    W, H, P, counts, dc, ds, os_, ig, oig = _c4_setup(qmc)
+    zero = torch.zeros(P, dtype=torch.float32, device="cuda")
+    m1, _, _ = qmc.qmc_integrate_pixels_l2_step(ds, ig, W, H, dc, zero)
+    torch.cuda.synchronize()
+    i32 = m1.cpu().numpy()
+    gpix = pick(P, 48, 49)
+    delta = np.random.default_rng(50).uniform(-0.02, 0.02, gpix.size) * np.abs(i32[gpix])
+    target = i32.copy()
+    target[gpix] = (i32[gpix].astype(np.float64) - delta).astype(np.float32)
+    m2, loss, g = qmc.qmc_integrate_pixels_l2_step(ds, ig, W, H, dc, torch.from_numpy(target).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(m2.cpu().numpy().view(np.uint32), i32.view(np.uint32))
+    pix = pick(P, 400, 51)
+    ref = estimator.integrate_pixels(os_, oig, counts, pix)
+    ok = _est_tol(i32[pix], ref)
+    assert ok.all(), (pix[~ok][:10], i32[pix][~ok][:5], ref["mean"][~ok][:5])
+    diff = i32[gpix].astype(np.float64) - target[gpix].astype(np.float64)
+    loss64 = float(np.sum(diff * diff)) / P
+    assert abs(float(loss.cpu()[0]) - loss64) <= 1e-4 * loss64
+    gvals = 2.0 * diff / P
+    g = g.cpu().numpy().astype(np.float64)
+    g64 = estimator.lobes_gradient(os_, oig, counts, gpix, gvals)
+    size = estimator.lobes_gradient(os_, oig, counts, gpix, gvals, sizes=True)
+    ok = _confined_grad_ok(g, g64, size)
+    assert ok.all(), (np.nonzero(~ok)[0][:10], g[~ok][:5], g64[~ok][:5], size[~ok][:5])
