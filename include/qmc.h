@@ -309,7 +309,10 @@ typedef struct {
 /* Bytes of device workspace needed by qmc_integrate_pixels (backward = 0), by
  * qmc_integrate_pixels_backward (backward = 1) or by qmc_integrate_pixels_l2_step
  * (backward = 2) for this problem, in *bytes.  The workspace holds a work counter and, for
- * the adjoint, per-task partial gradients and their FP64 chunk sums.
+ * the adjoint, partial gradients and their FP64 chunk sums: the tiles of 64 pixels are dealt
+ * into R = min(tiles, 4096, max(256, 48 MiB / (4 n_row))) slots (tile t to slot t mod R; n_row =
+ * n_theta, plus 1 for the L2 step), one row of n_row floats each, so the workspace is bounded
+ * by the parameter count and not by the image size (about 48 MiB at most for n_theta <= 49151).
  * Errors: INVALID_ARGUMENT (NULL), UNSUPPORTED (kind/dimension combination). */
 qmc_status qmc_workspace_size(qmc_context ctx, const qmc_sampler* sampler, const qmc_integrand* integrand,
                               uint32_t width, uint32_t height, int backward, size_t* bytes);
@@ -332,9 +335,10 @@ qmc_status qmc_integrate_pixels(qmc_context ctx, qmc_stream stream, const qmc_sa
 /* Adjoint of qmc_integrate_pixels for QMC_F_LOBES: given grad_means[p] = dL/dI_p, adds
  *   dL/dtheta = sum_p grad_means[p] / N_p * sum_{i in window} df_p(x_{p,i}) / dtheta
  * to grad_params[L*(2d+1)] (device float32; the caller zeroes it for a fresh gradient).
- * Samples are recomputed from (p, i) rather than stored.  Partial gradients are reduced
- * in FP64 in a fixed order, so the result is bitwise reproducible for a given launch
- * configuration.  workspace: >= qmc_workspace_size(..., 1) bytes.
+ * Samples are recomputed from (p, i) rather than stored.  Each slot's tiles are summed in
+ * tile order into its row and the rows are reduced in FP64 in slot order, so the result is
+ * bitwise reproducible and the same for every launch configuration.
+ * workspace: >= qmc_workspace_size(..., 1) bytes.
  * Errors as for qmc_integrate_pixels; UNSUPPORTED for integrands other than LOBES. */
 qmc_status qmc_integrate_pixels_backward(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
                                          const qmc_integrand* integrand, uint32_t width, uint32_t height,

@@ -22,8 +22,12 @@
 //     dimensions, so 32 lobes still fill a wavefront): t_j = fma(y_j, st_j, b_j) with
 //     st = sqrt(log2(e)/2) e^-l and b = -c st, E = sum t_j^2, G = exp2(-E).  The forward pass
 //     reduces across lanes once per pixel; the adjoint needs no cross-lane reduction at all
-//     and writes one partial gradient per task, which two further kernels sum in FP64 in
-//     task order.
+//     and adds its partial gradient into the row of the task's slot (below), which two
+//     further kernels sum in FP64 in slot order.
+// Adjoint slots: the tasks are dealt into a fixed number R of slots (task t to slot t mod R; R
+// depends only on the problem's size) and one wavefront runs all tasks of a slot in increasing
+// order, adding each task's partial into the slot's row.  The workspace then holds R rows
+// instead of one per task, and every row is the same whatever the launch shape.
 // Results never depend on which wavefront ran which task, so they are bitwise reproducible.
 #include <cmath>
 
@@ -42,7 +46,13 @@ constexpr uint32_t kQI = 26;     // stride entries for index bits 6..31
 constexpr uint32_t kBlock = 256;
 constexpr uint32_t kWavesPerBlock = kBlock / kWave;
 constexpr float kKappa = 0.84932180028801904f;  // sqrt(log2(e) / 2): exp(-r^2/2) = exp2(-(kKappa r)^2)
-constexpr uint32_t kChunkTasks = 256;           // tasks per first-level reduction block
+constexpr uint32_t kChunkTasks = 256;           // slot rows per first-level reduction block
+// Adjoint slots: at most kMaxSlots rows, and at most kSlotBytes of rows unless that leaves fewer
+// than kMinSlots (one per compute unit), so that rows take at most 48 MiB for every parameter
+// count up to 49152.
+constexpr uint32_t kMaxSlots = 4096;
+constexpr uint32_t kMinSlots = 256;
+constexpr size_t kSlotBytes = size_t(48) << 20;
 
 struct Args {
     // sampler
@@ -85,8 +95,9 @@ struct Args {
     uint32_t dynamic;
     uint32_t total_waves;
     // adjoint
-    float* partials;  // [num_tasks][n_theta]
+    float* partials;  // [num_slots][n_row]: n_theta entries (+ the loss sum for the L2 step)
     uint32_t n_theta;
+    uint32_t num_slots;
 };
 
 // -------------------------------------------------------------- wave helpers ----
@@ -620,6 +631,22 @@ __device__ __forceinline__ void for_each_task(const Args& a, F&& body) {
     }
 }
 
+// Runs body(task, slot, first) for every task of every slot this wavefront obtains: slot r holds
+// the tasks r, r + R, r + 2R, ... (R = num_slots), visited in that order; first marks the slot's
+// first task, whose partial initialises the slot's row.
+template <typename F>
+__device__ __forceinline__ void for_each_slot_task(const Args& a, F&& body) {
+    const uint32_t wave_global = blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint32_t it = 0;; ++it) {
+        const uint32_t slot = next_task(a, wave_global, it);
+        if (slot >= a.num_slots) break;
+        for (uint32_t task = slot; task < a.num_tasks; task += a.num_slots) body(task, slot, task == slot);
+    }
+}
+
+// row[e] = v on a slot's first task, else row[e] + v (each entry has one owner lane).
+__device__ __forceinline__ void slot_store(float* row, float v, bool first) { *row = first ? v : *row + v; }
+
 // ------------------------------------------------------------ Genz forward ----
 
 // Genz product f(x) = exp(-sum_{j<4} a_j^2 (x_j - u_j)^2) * cos(2 pi u_4 + sum_{j>=4} a_j x_j),
@@ -905,11 +932,12 @@ __global__ __launch_bounds__(kBlock) void lobes_fwd(Args a) {
 // ---------------------------------------------------------- lobes adjoint ----
 
 // Adds sum over the tile's samples of gscale(pixel) * d f / d theta into out[0 .. n_theta)
-// (c and l entries still carry the factor kKappa^2 that the reduction removes).
+// (c and l entries still carry the factor kKappa^2 that the reduction removes); with `first`
+// the row is written instead of added to.
 template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK>
 __device__ __forceinline__ void lobes_bwd_tile(const Args& a, const SamplerLds<D>& S, PixelLds<D>& PX,
                                                StageLds<D>& ST, uint32_t task, const TileInfo& ti, float gscale,
-                                               float* out) {
+                                               float* out, bool first) {
     using LL = LobeLayout<D>;
     const uint32_t lane = lane_id();
     const uint32_t half = lane / LL::LPG;
@@ -968,11 +996,11 @@ __device__ __forceinline__ void lobes_bwd_tile(const Args& a, const SamplerLds<D
 #pragma unroll
             for (int jj = 0; jj < LL::DH; ++jj) {
                 if (half * LL::DH + jj < d) {
-                    oc[jj] = acc_c[jj] * st[jj];
-                    ol[jj] = acc_l[jj];
+                    slot_store(&oc[jj], acc_c[jj] * st[jj], first);
+                    slot_store(&ol[jj], acc_l[jj], first);
                 }
             }
-            if (half == 0) out[2 * L * d + lobe] = acc_w;
+            if (half == 0) slot_store(&out[2 * L * d + lobe], acc_w, first);
         }
     }
 }
@@ -985,12 +1013,12 @@ __global__ __launch_bounds__(kBlock) void lobes_bwd(Args a) {
     stage_sampler<D, SK, NUS>(S, a);
     __syncthreads();
     const uint32_t wv = threadIdx.x >> 6;
-    for_each_task(a, [&](uint32_t task) {
+    for_each_slot_task(a, [&](uint32_t task, uint32_t slot, bool first) {
         const TileInfo ti = tile_info(a, task);
         const uint32_t N = ti.inb ? a.counts[ti.p] : 0u;
         const float gscale = (ti.inb && N) ? a.grad_means[ti.p] / static_cast<float>(N) : 0.0f;
         lobes_bwd_tile<D, SK, NUS, SHIFT, BACK>(a, S, PXs[wv], STs[wv], task, ti, gscale,
-                                                a.partials + uint64_t(task) * a.n_theta);
+                                                a.partials + uint64_t(slot) * a.n_theta, first);
     });
 }
 
@@ -1020,9 +1048,9 @@ __global__ __launch_bounds__(kBlock) void lobes_step(Args a) {
     const uint32_t lane = lane_id();
     const uint32_t half = lane / LL::LPG;
     const float invP = 1.0f / static_cast<float>(a.num_pixels);
-    for_each_task(a, [&](uint32_t task) {
+    for_each_slot_task(a, [&](uint32_t task, uint32_t slot, bool first) {
         const TileInfo ti = tile_info(a, task);
-        float* out = a.partials + uint64_t(task) * (a.n_theta + 1);
+        float* out = a.partials + uint64_t(slot) * (a.n_theta + 1);
         if constexpr (SINGLE) {
             // (1) Packed pixels (fewer than 64 samples): forward sums first, so that their
             // samples carry a known scale dL/dI_p / N_p through the adjoint walk below.
@@ -1112,13 +1140,13 @@ __global__ __launch_bounds__(kBlock) void lobes_step(Args a) {
 #pragma unroll
                 for (int jj = 0; jj < LL::DH; ++jj) {
                     if (half * LL::DH + jj < d) {
-                        oc[jj] = acc[jj][lane] * st[jj];
-                        ol[jj] = acc[LL::DH + jj][lane];
+                        slot_store(&oc[jj], acc[jj][lane] * st[jj], first);
+                        slot_store(&ol[jj], acc[LL::DH + jj][lane], first);
                     }
                 }
-                if (half == 0) out[2 * L * d + lobe] = acc[2 * LL::DH][lane];
+                if (half == 0) slot_store(&out[2 * L * d + lobe], acc[2 * LL::DH][lane], first);
             }
-            if (lane == 0) out[a.n_theta] = loss;
+            if (lane == 0) slot_store(&out[a.n_theta], loss, first);
             wave_sync();
         } else {
             // forward walk over every lobe group, per-pixel loss gradient, adjoint walk
@@ -1134,23 +1162,23 @@ __global__ __launch_bounds__(kBlock) void lobes_step(Args a) {
             }
             const float loss = wave_sum(sq);
             wave_sync();
-            lobes_bwd_tile<D, SK, NUS, SHIFT, BACK>(a, S, PX, ST, task, ti, gscale, out);
-            if (lane == 0) out[a.n_theta] = loss;
+            lobes_bwd_tile<D, SK, NUS, SHIFT, BACK>(a, S, PX, ST, task, ti, gscale, out, first);
+            if (lane == 0) slot_store(&out[a.n_theta], loss, first);
         }
     });
 }
 
-// First reduction level: block (x = 64-parameter tile, y = chunk of kChunkTasks tasks) sums
-// its tasks in FP64; wave w takes tasks w, w+4, ... of the chunk and the four wave sums are
+// First reduction level: block (x = 64-parameter tile, y = chunk of kChunkTasks slot rows) sums
+// its rows in FP64; wave w takes rows w, w+4, ... of the chunk and the four wave sums are
 // combined in wave order.  Output: chunk_sums[chunk][e].
 __global__ __launch_bounds__(256) void reduce_partials_chunks(const float* __restrict__ partials,
-                                                              uint32_t num_tasks, uint32_t n_theta,
+                                                              uint32_t num_rows, uint32_t n_theta,
                                                               double* __restrict__ chunk_sums) {
     __shared__ double part[4][64];
     const uint32_t e = blockIdx.x * 64 + (threadIdx.x & 63u);
     const uint32_t w = threadIdx.x >> 6;
     const uint32_t t0 = blockIdx.y * kChunkTasks;
-    const uint32_t t1 = min(t0 + kChunkTasks, num_tasks);
+    const uint32_t t1 = min(t0 + kChunkTasks, num_rows);
     double acc = 0.0;
     if (e < n_theta)
         for (uint32_t t = t0 + w; t < t1; t += 4) acc += static_cast<double>(partials[uint64_t(t) * n_theta + e]);
@@ -1265,18 +1293,26 @@ __global__ __launch_bounds__(256) void scan_add(uint64_t* __restrict__ offsets, 
 
 struct Plan {
     size_t queue_off = 0, partials_off = 256, chunks_off = 256, total = 256;
-    uint32_t num_tasks = 0, num_chunks = 0, n_theta = 0, n_row = 0;
+    uint32_t num_tasks = 0, num_slots = 0, num_chunks = 0, n_theta = 0, n_row = 0;
 };
+
+// Adjoint slots for a problem of num_tasks tasks and rows of n_row floats (see the top of file).
+uint32_t num_slots_for(uint32_t num_tasks, uint32_t n_row) {
+    const size_t by_bytes = kSlotBytes / (size_t(4) * std::max<uint32_t>(n_row, 1));
+    const size_t r = std::min<size_t>(kMaxSlots, std::max<size_t>(by_bytes, kMinSlots));
+    return static_cast<uint32_t>(std::max<size_t>(1, std::min<size_t>(r, num_tasks)));
+}
 
 // mode: 0 forward, 1 adjoint, 2 fused L2 step (partial rows carry one extra loss entry).
 Plan make_plan(const qmc_integrand* ig, uint32_t P, int mode) {
     Plan pl;
     pl.num_tasks = (P + kTile - 1) / kTile;
-    pl.num_chunks = (pl.num_tasks + kChunkTasks - 1) / kChunkTasks;
     if (ig && ig->kind == QMC_F_LOBES) pl.n_theta = ig->num_lobes * (2 * ig->d + 1);
     pl.n_row = pl.n_theta + (mode == 2 ? 1u : 0u);
     if (mode != 0) {
-        pl.chunks_off = (pl.partials_off + size_t(pl.num_tasks) * pl.n_row * 4 + 255) & ~size_t(255);
+        pl.num_slots = num_slots_for(pl.num_tasks, pl.n_row);
+        pl.num_chunks = (pl.num_slots + kChunkTasks - 1) / kChunkTasks;
+        pl.chunks_off = (pl.partials_off + size_t(pl.num_slots) * pl.n_row * 4 + 255) & ~size_t(255);
         pl.total = pl.chunks_off + size_t(pl.num_chunks) * pl.n_row * 8;
     }
     return pl;
@@ -1500,7 +1536,10 @@ qmc_status integrate_common(const char* who, qmc_context ctx, qmc_stream stream,
     a.queue = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.queue_off);
     a.partials = reinterpret_cast<float*>(static_cast<char*>(ws) + pl.partials_off);
     a.n_theta = pl.n_theta;
-    const uint32_t grid = persistent_grid(ctx, integrate_tune(ctx, ig->kind, ig->d, backward), pl.num_tasks, &a);
+    a.num_slots = pl.num_slots;
+    // the adjoint's work items are its slots: no more wavefronts than slots
+    const uint32_t grid = persistent_grid(ctx, integrate_tune(ctx, ig->kind, ig->d, backward),
+                                          backward ? pl.num_slots : pl.num_tasks, &a);
     const bool nus = (sp->flags & QMC_PIXEL_NUS) != 0, shift = (sp->flags & QMC_PIXEL_SHIFT) != 0;
     const bool back = (sp->flags & QMC_LATTICE_BACKWARD) != 0;
     clear_launch_error();
@@ -1530,7 +1569,7 @@ qmc_status integrate_common(const char* who, qmc_context ctx, qmc_stream stream,
         }
         double* chunk_sums = reinterpret_cast<double*>(static_cast<char*>(ws) + pl.chunks_off);
         hipLaunchKernelGGL(reduce_partials_chunks, dim3((pl.n_row + 63) / 64, pl.num_chunks), dim3(256), 0, hs,
-                           a.partials, pl.num_tasks, pl.n_row, chunk_sums);
+                           a.partials, pl.num_slots, pl.n_row, chunk_sums);
         hipLaunchKernelGGL(reduce_chunks, dim3((pl.n_row + 255) / 256), dim3(256), 0, hs, chunk_sums, pl.num_chunks,
                            pl.n_row, pl.n_theta, ig->num_lobes * ig->d, grad_params, mode == 2 ? sums : nullptr, P);
     }

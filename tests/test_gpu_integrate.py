@@ -551,3 +551,56 @@ def test_full_size_fused_l2_step_sampled_pixels(qmc):
     size = estimator.lobes_gradient(os_, oig, counts, gpix, gvals, sizes=True)
     ok = _confined_grad_ok(g, g64, size)
     assert ok.all(), (np.nonzero(~ok)[0][:10], g[~ok][:5], g64[~ok][:5], size[~ok][:5])
+
+
+@pytest.mark.parametrize("d,L,W,H", [(8, 64, 40, 30), (64, 32, 20, 13)])
+def test_adjoint_is_schedule_independent(qmc, d, L, W, H, tmp_path):
+    """The adjoint and the fused L2 step give bitwise the same results under every launch shape
+    (persistent grid of 1 to 32 wavefronts per compute unit, static or queued): each partial-sum
+    row covers a fixed set of tasks in a fixed order whatever wavefront runs it."""
+    import json
+
+    import torch
+
+    P = W * H
+    counts = _counts_edge(P)
+    theta, dtheta = _lobes_setup(qmc, L, d)
+    ds, _ = _sampler_pair(qmc, "sobol", max(d, 8), 21, NUS | SHIFT)
+    ig = qmc.PixelIntegrand.lobes(dtheta, L, d, 9)
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    gm = torch.from_numpy(np.random.default_rng(3).uniform(-1, 1, P).astype(np.float32) / P).cuda()
+    target = torch.from_numpy(np.random.default_rng(4).uniform(0, 1, P).astype(np.float32)).cuda()
+    key = (qmc.QMC_F_LOBES << 16) | (d << 1) | 1
+    saved = tmp_path / "saved.json"
+    qmc.qmc_tune_save(str(saved))
+    results = []
+    try:
+        for w, dyn in ((1, 0), (4, 1), (16, 0), (32, 1)):
+            f = tmp_path / ("tune_%d_%d.json" % (w, dyn))
+            cfg = {"chunks_per_wave": 1, "nontemporal": 0}
+            f.write_text(json.dumps({"sobol": cfg, "lattice": cfg,
+                                     "integrate": [{"key": key, "waves_per_cu": w, "dynamic": dyn}]}))
+            qmc.qmc_tune_load(str(f))
+            g = qmc.qmc_integrate_pixels_backward(ds, ig, W, H, dc, gm)
+            _, loss, sg = qmc.qmc_integrate_pixels_l2_step(ds, ig, W, H, dc, target)
+            torch.cuda.synchronize()
+            results.append([t.cpu().numpy().view(np.uint32) for t in (g, loss, sg)])
+    finally:
+        qmc.qmc_tune_load(str(saved))
+    for r in results[1:]:
+        for a, b in zip(results[0], r):
+            assert np.array_equal(a, b)
+
+
+def test_adjoint_workspace_is_bounded(qmc):
+    """Partial-sum rows are bounded by the slot count, not the frame size: the 3840x2160 adjoint
+    with 32 lobes in 64 dimensions (4128 parameters) needs under 100 MB of workspace."""
+    import torch
+
+    m = _mats(64)
+    ds = qmc.PixelSampler.sobol(qmc.from_u32(m), 1, NUS | SHIFT)
+    ig = qmc.PixelIntegrand.lobes(torch.zeros(32 * 129, device="cuda"), 32, 64, 9)
+    for mode in (1, 2):
+        assert qmc.qmc_workspace_size(ds, ig, 3840, 2160, mode) < 100e6
+    ig8 = qmc.PixelIntegrand.lobes(torch.zeros(64 * 17, device="cuda"), 64, 8, 9)
+    assert qmc.qmc_workspace_size(ds, ig8, 1920, 1080, 1) < 20e6
