@@ -309,10 +309,9 @@ typedef struct {
 /* Bytes of device workspace needed by qmc_integrate_pixels (backward = 0), by
  * qmc_integrate_pixels_backward (backward = 1) or by qmc_integrate_pixels_l2_step
  * (backward = 2) for this problem, in *bytes.  The workspace holds a work counter and, for
- * the adjoint, partial gradients and their FP64 chunk sums: the tiles of 64 pixels are dealt
- * into R = min(tiles, 4096, max(256, 48 MiB / (4 n_row))) slots (tile t to slot t mod R; n_row =
- * n_theta, plus 1 for the L2 step), one row of n_row floats each, so the workspace is bounded
- * by the parameter count and not by the image size (about 48 MiB at most for n_theta <= 49151).
+ * the adjoint, an exact accumulator of 640 bytes per gradient entry (n_theta entries, plus the
+ * loss for the L2 step): 256 + 640 * n_row bytes, bounded by the parameter count and not by the
+ * image size (2.6 MB for 4128 parameters).
  * Errors: INVALID_ARGUMENT (NULL), UNSUPPORTED (kind/dimension combination). */
 qmc_status qmc_workspace_size(qmc_context ctx, const qmc_sampler* sampler, const qmc_integrand* integrand,
                               uint32_t width, uint32_t height, int backward, size_t* bytes);
@@ -335,9 +334,10 @@ qmc_status qmc_integrate_pixels(qmc_context ctx, qmc_stream stream, const qmc_sa
 /* Adjoint of qmc_integrate_pixels for QMC_F_LOBES: given grad_means[p] = dL/dI_p, adds
  *   dL/dtheta = sum_p grad_means[p] / N_p * sum_{i in window} df_p(x_{p,i}) / dtheta
  * to grad_params[L*(2d+1)] (device float32; the caller zeroes it for a fresh gradient).
- * Samples are recomputed from (p, i) rather than stored.  Each slot's tiles are summed in
- * tile order into its row and the rows are reduced in FP64 in slot order, so the result is
- * bitwise reproducible and the same for every launch configuration.
+ * Samples are recomputed from (p, i) rather than stored.  Each tile of 64 pixels forms its
+ * float32 partial gradient; the partials are summed exactly (as integer multiples of 2^-149 in
+ * 64-bit words) and the exact sum is rounded once, so the result is bitwise reproducible and the
+ * same for every launch configuration and schedule.
  * workspace: >= qmc_workspace_size(..., 1) bytes.
  * Errors as for qmc_integrate_pixels; UNSUPPORTED for integrands other than LOBES. */
 qmc_status qmc_integrate_pixels_backward(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
@@ -348,8 +348,8 @@ qmc_status qmc_integrate_pixels_backward(qmc_context ctx, qmc_stream stream, con
 
 /* One fused training step for the per-pixel L2 loss L = (1/P) sum_p (I_p - T_p)^2 of the
  * lobe integrand over the full windows [0, N_p): estimates I_p, dL/dI_p = 2 (I_p - T_p) / P
- * and the adjoint of qmc_integrate_pixels_backward, in one launch (plus the fixed-order FP64
- * reduction).  The adjoint's per-pixel sums do not depend on dL/dI_p, only their scaling
+ * and the adjoint of qmc_integrate_pixels_backward, in one launch (plus the rounding of the
+ * exact sums of the gradient and of the loss).  The adjoint's per-pixel sums do not depend on dL/dI_p, only their scaling
  * does, so with at most 64 lobes (32 when d > 32) one pass over each pixel's samples
  * accumulates the estimate and the unscaled adjoint sums together and scales them when the
  * pixel is complete: samples are generated once.  With more lobes the forward pass over all

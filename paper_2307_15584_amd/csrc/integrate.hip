@@ -21,13 +21,15 @@
 //     samples is staged in LDS and every lane owns one lobe (for d > 32, half of a lobe's
 //     dimensions, so 32 lobes still fill a wavefront): t_j = fma(y_j, st_j, b_j) with
 //     st = sqrt(log2(e)/2) e^-l and b = -c st, E = sum t_j^2, G = exp2(-E).  The forward pass
-//     reduces across lanes once per pixel; the adjoint needs no cross-lane reduction at all
-//     and adds its partial gradient into the row of the task's slot (below), which two
-//     further kernels sum in FP64 in slot order.
-// Adjoint slots: the tasks are dealt into a fixed number R of slots (task t to slot t mod R; R
-// depends only on the problem's size) and one wavefront runs all tasks of a slot in increasing
-// order, adding each task's partial into the slot's row.  The workspace then holds R rows
-// instead of one per task, and every row is the same whatever the launch shape.
+//     reduces across lanes once per pixel; the adjoint needs no cross-lane reduction at all:
+//     at the end of a task each lane adds its lobe's partial gradient into an exact accumulator.
+// Exact accumulation: a float32 value is m 2^(e-150) with an integer m < 2^24, so it is an
+// integer multiple of 2^-149 below 2^128.  Each value is split into two 32-bit digits of that
+// integer (position fixed by its exponent) and the digits are added with 64-bit integer atomics
+// into nine int64 words per parameter (32-bit digit positions with 32 bits of headroom for
+// carries).  Integer addition is associative, so the sum is exact and the same whichever
+// wavefront added which task in which order; one final kernel propagates the carries and rounds
+// once to float.  Several copies of the words (by block) spread the atomics.
 // Results never depend on which wavefront ran which task, so they are bitwise reproducible.
 #include <cmath>
 
@@ -46,13 +48,11 @@ constexpr uint32_t kQI = 26;     // stride entries for index bits 6..31
 constexpr uint32_t kBlock = 256;
 constexpr uint32_t kWavesPerBlock = kBlock / kWave;
 constexpr float kKappa = 0.84932180028801904f;  // sqrt(log2(e) / 2): exp(-r^2/2) = exp2(-(kKappa r)^2)
-constexpr uint32_t kChunkTasks = 256;           // slot rows per first-level reduction block
-// Adjoint slots: at most kMaxSlots rows, and at most kSlotBytes of rows unless that leaves fewer
-// than kMinSlots (one per compute unit), so that rows take at most 48 MiB for every parameter
-// count up to 49152.
-constexpr uint32_t kMaxSlots = 4096;
-constexpr uint32_t kMinSlots = 256;
-constexpr size_t kSlotBytes = size_t(48) << 20;
+// Exact accumulator (see the top of file): digit words per parameter (nine for the digit
+// positions of finite floats, one counting non-finite values) and copies of the words.
+constexpr uint32_t kAccDigits = 9;
+constexpr uint32_t kAccWords = 10;
+constexpr uint32_t kAccCopies = 8;
 
 struct Args {
     // sampler
@@ -94,10 +94,10 @@ struct Args {
     uint32_t* queue;
     uint32_t dynamic;
     uint32_t total_waves;
-    // adjoint
-    float* partials;  // [num_slots][n_row]: n_theta entries (+ the loss sum for the L2 step)
-    uint32_t n_theta;
-    uint32_t num_slots;
+    // adjoint: exact accumulators [kAccCopies][n_row][kAccWords], n_row = n_theta (+1 for the
+    // loss sum of the L2 step)
+    unsigned long long* acc;
+    uint32_t n_theta, n_row;
 };
 
 // -------------------------------------------------------------- wave helpers ----
@@ -631,21 +631,27 @@ __device__ __forceinline__ void for_each_task(const Args& a, F&& body) {
     }
 }
 
-// Runs body(task, slot, first) for every task of every slot this wavefront obtains: slot r holds
-// the tasks r, r + R, r + 2R, ... (R = num_slots), visited in that order; first marks the slot's
-// first task, whose partial initialises the slot's row.
-template <typename F>
-__device__ __forceinline__ void for_each_slot_task(const Args& a, F&& body) {
-    const uint32_t wave_global = blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (uint32_t it = 0;; ++it) {
-        const uint32_t slot = next_task(a, wave_global, it);
-        if (slot >= a.num_slots) break;
-        for (uint32_t task = slot; task < a.num_tasks; task += a.num_slots) body(task, slot, task == slot);
-    }
+// Adds v exactly into accumulator entry e (its kAccWords words in this block's copy).  The
+// integer m 2^(pos mod 32), m the significand and pos = max(exponent field, 1) - 1, spans the
+// 32-bit digit positions k = pos / 32 and k + 1; both digits carry the sign of v.  Infinities
+// and NaNs add 1 to the last word instead, which makes the result NaN.  Branch-free: zeros add
+// zero digits.
+__device__ __forceinline__ void acc_add(const Args& a, uint32_t e, float v) {
+    unsigned long long* w = a.acc + (uint64_t(blockIdx.x % kAccCopies) * a.n_row + e) * kAccWords;
+    const uint32_t bits = __float_as_uint(v);
+    const uint32_t ex = (bits >> 23) & 0xFFu;
+    const uint32_t m = (bits & 0x7FFFFFu) | (ex ? 0x800000u : 0u);
+    const uint32_t pos = ex ? ex - 1u : 0u;
+    const uint32_t sh = pos & 31u;
+    const uint32_t lo = m << sh, hi = (m >> 1) >> (31u - sh);
+    const bool finite = ex != 0xFFu;
+    const bool neg = (bits >> 31) != 0;
+    const uint32_t k = finite ? (pos >> 5) : kAccWords - 2;
+    const unsigned long long dlo = finite ? (neg ? 0ull - lo : static_cast<unsigned long long>(lo)) : 0ull;
+    const unsigned long long dhi = finite ? (neg ? 0ull - hi : static_cast<unsigned long long>(hi)) : 1ull;
+    atomicAdd(&w[k], dlo);
+    atomicAdd(&w[k + 1], dhi);
 }
-
-// row[e] = v on a slot's first task, else row[e] + v (each entry has one owner lane).
-__device__ __forceinline__ void slot_store(float* row, float v, bool first) { *row = first ? v : *row + v; }
 
 // ------------------------------------------------------------ Genz forward ----
 
@@ -931,13 +937,11 @@ __global__ __launch_bounds__(kBlock) void lobes_fwd(Args a) {
 
 // ---------------------------------------------------------- lobes adjoint ----
 
-// Adds sum over the tile's samples of gscale(pixel) * d f / d theta into out[0 .. n_theta)
-// (c and l entries still carry the factor kKappa^2 that the reduction removes); with `first`
-// the row is written instead of added to.
+// Adds sum over the tile's samples of gscale(pixel) * d f / d theta into the accumulator
+// (c and l entries still carry the factor kKappa^2 that the final kernel removes).
 template <int D, uint32_t SK, bool NUS, bool SHIFT, bool BACK>
 __device__ __forceinline__ void lobes_bwd_tile(const Args& a, const SamplerLds<D>& S, PixelLds<D>& PX,
-                                               StageLds<D>& ST, uint32_t task, const TileInfo& ti, float gscale,
-                                               float* out, bool first) {
+                                               StageLds<D>& ST, uint32_t task, const TileInfo& ti, float gscale) {
     using LL = LobeLayout<D>;
     const uint32_t lane = lane_id();
     const uint32_t half = lane / LL::LPG;
@@ -991,16 +995,16 @@ __device__ __forceinline__ void lobes_bwd_tile(const Args& a, const SamplerLds<D
             [&](uint32_t) {});
         if (own) {
             const uint32_t d = a.d, L = a.L;
-            float* oc = out + uint64_t(lobe) * d + half * LL::DH;
-            float* ol = oc + uint64_t(L) * d;
+            uint32_t ec = lobe * d + half * LL::DH;
+            asm volatile("" : "+v"(ec));  // formed per task: keeps the entry addresses from being hoisted
 #pragma unroll
             for (int jj = 0; jj < LL::DH; ++jj) {
                 if (half * LL::DH + jj < d) {
-                    slot_store(&oc[jj], acc_c[jj] * st[jj], first);
-                    slot_store(&ol[jj], acc_l[jj], first);
+                    acc_add(a, ec + jj, acc_c[jj] * st[jj]);
+                    acc_add(a, L * d + ec + jj, acc_l[jj]);
                 }
             }
-            if (half == 0) slot_store(&out[2 * L * d + lobe], acc_w, first);
+            if (half == 0) acc_add(a, 2 * L * d + lobe, acc_w);
         }
     }
 }
@@ -1013,19 +1017,18 @@ __global__ __launch_bounds__(kBlock) void lobes_bwd(Args a) {
     stage_sampler<D, SK, NUS>(S, a);
     __syncthreads();
     const uint32_t wv = threadIdx.x >> 6;
-    for_each_slot_task(a, [&](uint32_t task, uint32_t slot, bool first) {
+    for_each_task(a, [&](uint32_t task) {
         const TileInfo ti = tile_info(a, task);
         const uint32_t N = ti.inb ? a.counts[ti.p] : 0u;
         const float gscale = (ti.inb && N) ? a.grad_means[ti.p] / static_cast<float>(N) : 0.0f;
-        lobes_bwd_tile<D, SK, NUS, SHIFT, BACK>(a, S, PXs[wv], STs[wv], task, ti, gscale,
-                                                a.partials + uint64_t(slot) * a.n_theta, first);
+        lobes_bwd_tile<D, SK, NUS, SHIFT, BACK>(a, S, PXs[wv], STs[wv], task, ti, gscale);
     });
 }
 
 // ------------------------------------------------------ fused L2 training step ----
 //
 // L = (1/P) sum_p (I_p - T_p)^2: the estimate of each pixel, dL/dI_p = 2 (I_p - T_p) / P and
-// the adjoint over the same samples in one kernel.  Partial rows hold [dL/dtheta, loss sum].
+// the adjoint over the same samples in one kernel.  Accumulator entries: [dL/dtheta, loss sum].
 // The adjoint's per-pixel sums  sum_i G,  sum_i w G t_j  and  sum_i w G t_j^2  do not depend on
 // dL/dI_p, only their final scaling does.  When all lobes fit one lane group (SINGLE), a big
 // pixel's samples are generated once and feed the estimate and these sums together; packed
@@ -1048,9 +1051,8 @@ __global__ __launch_bounds__(kBlock) void lobes_step(Args a) {
     const uint32_t lane = lane_id();
     const uint32_t half = lane / LL::LPG;
     const float invP = 1.0f / static_cast<float>(a.num_pixels);
-    for_each_slot_task(a, [&](uint32_t task, uint32_t slot, bool first) {
+    for_each_task(a, [&](uint32_t task) {
         const TileInfo ti = tile_info(a, task);
-        float* out = a.partials + uint64_t(slot) * (a.n_theta + 1);
         if constexpr (SINGLE) {
             // (1) Packed pixels (fewer than 64 samples): forward sums first, so that their
             // samples carry a known scale dL/dI_p / N_p through the adjoint walk below.
@@ -1135,18 +1137,18 @@ __global__ __launch_bounds__(kBlock) void lobes_step(Args a) {
             add_sums(1.0f);  // packed samples: already scaled
             if (own) {
                 const uint32_t d = a.d, L = a.L;
-                float* oc = out + uint64_t(lobe) * d + half * LL::DH;
-                float* ol = oc + uint64_t(L) * d;
+                uint32_t ec = lobe * d + half * LL::DH;
+                asm volatile("" : "+v"(ec));  // formed per task: keeps the entry addresses from being hoisted
 #pragma unroll
                 for (int jj = 0; jj < LL::DH; ++jj) {
                     if (half * LL::DH + jj < d) {
-                        slot_store(&oc[jj], acc[jj][lane] * st[jj], first);
-                        slot_store(&ol[jj], acc[LL::DH + jj][lane], first);
+                        acc_add(a, ec + jj, acc[jj][lane] * st[jj]);
+                        acc_add(a, L * d + ec + jj, acc[LL::DH + jj][lane]);
                     }
                 }
-                if (half == 0) slot_store(&out[2 * L * d + lobe], acc[2 * LL::DH][lane], first);
+                if (half == 0) acc_add(a, 2 * L * d + lobe, acc[2 * LL::DH][lane]);
             }
-            if (lane == 0) slot_store(&out[a.n_theta], loss, first);
+            if (lane == 0) acc_add(a, a.n_theta, loss);
             wave_sync();
         } else {
             // forward walk over every lobe group, per-pixel loss gradient, adjoint walk
@@ -1162,49 +1164,50 @@ __global__ __launch_bounds__(kBlock) void lobes_step(Args a) {
             }
             const float loss = wave_sum(sq);
             wave_sync();
-            lobes_bwd_tile<D, SK, NUS, SHIFT, BACK>(a, S, PX, ST, task, ti, gscale, out, first);
-            if (lane == 0) slot_store(&out[a.n_theta], loss, first);
+            lobes_bwd_tile<D, SK, NUS, SHIFT, BACK>(a, S, PX, ST, task, ti, gscale);
+            if (lane == 0) acc_add(a, a.n_theta, loss);
         }
     });
 }
 
-// First reduction level: block (x = 64-parameter tile, y = chunk of kChunkTasks slot rows) sums
-// its rows in FP64; wave w takes rows w, w+4, ... of the chunk and the four wave sums are
-// combined in wave order.  Output: chunk_sums[chunk][e].
-__global__ __launch_bounds__(256) void reduce_partials_chunks(const float* __restrict__ partials,
-                                                              uint32_t num_rows, uint32_t n_theta,
-                                                              double* __restrict__ chunk_sums) {
-    __shared__ double part[4][64];
-    const uint32_t e = blockIdx.x * 64 + (threadIdx.x & 63u);
-    const uint32_t w = threadIdx.x >> 6;
-    const uint32_t t0 = blockIdx.y * kChunkTasks;
-    const uint32_t t1 = min(t0 + kChunkTasks, num_rows);
-    double acc = 0.0;
-    if (e < n_theta)
-        for (uint32_t t = t0 + w; t < t1; t += 4) acc += static_cast<double>(partials[uint64_t(t) * n_theta + e]);
-    part[w][threadIdx.x & 63u] = acc;
-    __syncthreads();
-    if (w == 0 && e < n_theta) {
-        const uint32_t l = threadIdx.x & 63u;
-        chunk_sums[uint64_t(blockIdx.y) * n_theta + e] = ((part[0][l] + part[1][l]) + part[2][l]) + part[3][l];
-    }
+// Clears n words (a kernel rather than a memset, so that graph captures replay it correctly).
+__global__ __launch_bounds__(256) void zero_words(unsigned long long* __restrict__ w, uint64_t n) {
+    for (uint64_t i = blockIdx.x * uint64_t(256) + threadIdx.x; i < n; i += uint64_t(gridDim.x) * 256) w[i] = 0ull;
 }
 
-// Second level: grad[e] += scale_e * sum over chunks in chunk order; the centre and log-width
-// entries carry the factor 1/kKappa^2 of the exp2 form.  Rows of n_row = n_theta (+1 with a
-// loss sum in the last entry, which is added to *loss as a mean over the pixels).
-__global__ void reduce_chunks(const double* __restrict__ chunk_sums, uint32_t num_chunks, uint32_t n_row,
-                              uint32_t n_theta, uint32_t LD, float* __restrict__ grad, float* __restrict__ loss,
-                              uint32_t num_pixels) {
+// Final step of the exact accumulation: entry e = sum of its digits over the copies (int64, exact),
+// carries propagated so that digits 0..7 lie in [0, 2^32) and the top one holds the sign, then
+// value = sum_k digit_k 2^(32k - 149), formed from the top digit down in FP64.  grad[e] += value
+// times the entry's scale (1/kKappa^2 for centres and log-widths); the loss entry (e = n_theta,
+// L2 step) adds value / P to *loss.  A non-finite addend makes the entry NaN.
+__global__ __launch_bounds__(256) void acc_finalize(const unsigned long long* __restrict__ acc, uint32_t n_row,
+                                                    uint32_t n_theta, uint32_t LD, float* __restrict__ grad,
+                                                    float* __restrict__ loss, uint32_t num_pixels) {
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_row) return;
-    double acc = 0.0;
-    for (uint32_t c = 0; c < num_chunks; ++c) acc += chunk_sums[uint64_t(c) * n_row + e];
+    long long dg[kAccWords];
+#pragma unroll
+    for (uint32_t k = 0; k < kAccWords; ++k) dg[k] = 0;
+    for (uint32_t c = 0; c < kAccCopies; ++c) {
+        const unsigned long long* w = acc + (uint64_t(c) * n_row + e) * kAccWords;
+#pragma unroll
+        for (uint32_t k = 0; k < kAccWords; ++k) dg[k] += static_cast<long long>(w[k]);
+    }
+#pragma unroll
+    for (uint32_t k = 0; k + 1 < kAccDigits; ++k) {
+        const long long carry = dg[k] >> 32;  // floor division by 2^32
+        dg[k] -= carry * 4294967296ll;
+        dg[k + 1] += carry;
+    }
+    double v = static_cast<double>(dg[kAccDigits - 1]);
+    for (int k = static_cast<int>(kAccDigits) - 2; k >= 0; --k) v = v * 4294967296.0 + static_cast<double>(dg[k]);
+    v = ldexp(v, -149);
+    if (dg[kAccWords - 1] != 0) v = __builtin_nan("");
     if (e < n_theta) {
         const double scale = e < 2 * LD ? 1.0 / (static_cast<double>(kKappa) * kKappa) : 1.0;
-        grad[e] += static_cast<float>(acc * scale);
+        grad[e] += static_cast<float>(v * scale);
     } else if (loss) {
-        *loss += static_cast<float>(acc / num_pixels);
+        *loss += static_cast<float>(v / num_pixels);
     }
 }
 
@@ -1291,17 +1294,12 @@ __global__ __launch_bounds__(256) void scan_add(uint64_t* __restrict__ offsets, 
 
 // -------------------------------------------------------------------- host ----
 
+// Workspace: the work counter (256 bytes), then for the adjoint the exact accumulator.
 struct Plan {
-    size_t queue_off = 0, partials_off = 256, chunks_off = 256, total = 256;
-    uint32_t num_tasks = 0, num_slots = 0, num_chunks = 0, n_theta = 0, n_row = 0;
+    size_t queue_off = 0, acc_off = 256, total = 256;
+    uint32_t num_tasks = 0, n_theta = 0, n_row = 0;
+    uint64_t acc_words = 0;
 };
-
-// Adjoint slots for a problem of num_tasks tasks and rows of n_row floats (see the top of file).
-uint32_t num_slots_for(uint32_t num_tasks, uint32_t n_row) {
-    const size_t by_bytes = kSlotBytes / (size_t(4) * std::max<uint32_t>(n_row, 1));
-    const size_t r = std::min<size_t>(kMaxSlots, std::max<size_t>(by_bytes, kMinSlots));
-    return static_cast<uint32_t>(std::max<size_t>(1, std::min<size_t>(r, num_tasks)));
-}
 
 // mode: 0 forward, 1 adjoint, 2 fused L2 step (partial rows carry one extra loss entry).
 Plan make_plan(const qmc_integrand* ig, uint32_t P, int mode) {
@@ -1310,10 +1308,8 @@ Plan make_plan(const qmc_integrand* ig, uint32_t P, int mode) {
     if (ig && ig->kind == QMC_F_LOBES) pl.n_theta = ig->num_lobes * (2 * ig->d + 1);
     pl.n_row = pl.n_theta + (mode == 2 ? 1u : 0u);
     if (mode != 0) {
-        pl.num_slots = num_slots_for(pl.num_tasks, pl.n_row);
-        pl.num_chunks = (pl.num_slots + kChunkTasks - 1) / kChunkTasks;
-        pl.chunks_off = (pl.partials_off + size_t(pl.num_slots) * pl.n_row * 4 + 255) & ~size_t(255);
-        pl.total = pl.chunks_off + size_t(pl.num_chunks) * pl.n_row * 8;
+        pl.acc_words = uint64_t(kAccCopies) * pl.n_row * kAccWords;
+        pl.total = pl.acc_off + pl.acc_words * 8;
     }
     return pl;
 }
@@ -1534,16 +1530,18 @@ qmc_status integrate_common(const char* who, qmc_context ctx, qmc_stream stream,
     a.grad_means = mode == 2 ? nullptr : grad_means;
     a.target = mode == 2 ? grad_means : nullptr;
     a.queue = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.queue_off);
-    a.partials = reinterpret_cast<float*>(static_cast<char*>(ws) + pl.partials_off);
+    a.acc = reinterpret_cast<unsigned long long*>(static_cast<char*>(ws) + pl.acc_off);
     a.n_theta = pl.n_theta;
-    a.num_slots = pl.num_slots;
-    // the adjoint's work items are its slots: no more wavefronts than slots
-    const uint32_t grid = persistent_grid(ctx, integrate_tune(ctx, ig->kind, ig->d, backward),
-                                          backward ? pl.num_slots : pl.num_tasks, &a);
+    a.n_row = pl.n_row;
+    const uint32_t grid = persistent_grid(ctx, integrate_tune(ctx, ig->kind, ig->d, backward), pl.num_tasks, &a);
     const bool nus = (sp->flags & QMC_PIXEL_NUS) != 0, shift = (sp->flags & QMC_PIXEL_SHIFT) != 0;
     const bool back = (sp->flags & QMC_LATTICE_BACKWARD) != 0;
     clear_launch_error();
     if (a.dynamic) hipLaunchKernelGGL(reset_queue, dim3(1), dim3(1), 0, hs, a.queue);
+    if (backward) {
+        const uint32_t zb = static_cast<uint32_t>(std::min<uint64_t>((pl.acc_words + 255) / 256, 1024));
+        hipLaunchKernelGGL(zero_words, dim3(zb), dim3(256), 0, hs, a.acc, pl.acc_words);
+    }
     if (!backward) {
         if (ig->kind == QMC_F_GENZ)
             dispatch_sampler<GenzFam>(sp->kind, nus, shift, back, grid, hs, a);
@@ -1567,11 +1565,8 @@ qmc_status integrate_common(const char* who, qmc_context ctx, qmc_stream stream,
             // a pixel's unscaled sums, so the step runs the forward walk, then the adjoint walk.
             dispatch_sampler<LobesStepFam<64, false>>(sp->kind, nus, shift, back, grid, hs, a);
         }
-        double* chunk_sums = reinterpret_cast<double*>(static_cast<char*>(ws) + pl.chunks_off);
-        hipLaunchKernelGGL(reduce_partials_chunks, dim3((pl.n_row + 63) / 64, pl.num_chunks), dim3(256), 0, hs,
-                           a.partials, pl.num_slots, pl.n_row, chunk_sums);
-        hipLaunchKernelGGL(reduce_chunks, dim3((pl.n_row + 255) / 256), dim3(256), 0, hs, chunk_sums, pl.num_chunks,
-                           pl.n_row, pl.n_theta, ig->num_lobes * ig->d, grad_params, mode == 2 ? sums : nullptr, P);
+        hipLaunchKernelGGL(acc_finalize, dim3((pl.n_row + 255) / 256), dim3(256), 0, hs, a.acc, pl.n_row, pl.n_theta,
+                           ig->num_lobes * ig->d, grad_params, mode == 2 ? sums : nullptr, P);
     }
     return check_launch(who);
 }
