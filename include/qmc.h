@@ -363,6 +363,24 @@ qmc_status qmc_integrate_pixels_l2_step(qmc_context ctx, qmc_stream stream, cons
                                         const uint32_t* counts, const float* target, float* means, float* loss,
                                         float* grad_params, void* workspace, size_t workspace_bytes);
 
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid allocation.  The same step as
+ * qmc_integrate_pixels_l2_step (same kernels, bitwise the same results) without a workspace
+ * argument: its work counter and exact accumulator live in the library's static scratch of
+ * QMC_STATIC_SCRATCH_BYTES per device (held by every device the library runs on until the
+ * process ends).  The call allocates nothing and launches kernels only.  Limit: the problem's
+ * qmc_workspace_size(..., 2), 256 + 640 (L (2d+1) + 1) bytes, must not exceed
+ * QMC_STATIC_SCRATCH_BYTES, i.e. L (2d+1) <= 6552 parameters; larger problems fail with
+ * WORKSPACE before anything is enqueued.  Every call on one device shares that device's scratch
+ * and clears what it needs at its start, so calls that overlap on one GPU (other streams, other
+ * threads, other contexts of the device) race and must be ordered by the caller.
+ * Arguments, outputs and the other errors as for qmc_integrate_pixels_l2_step. */
+#define QMC_STATIC_SCRATCH_BYTES (4u << 20)
+qmc_status qmc_integrate_pixels_l2_step_noalloc(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler,
+                                                const qmc_integrand* integrand, uint32_t width, uint32_t height,
+                                                const uint32_t* counts, const float* target, float* means,
+                                                float* loss, float* grad_params);
+
 /* Exclusive prefix sums of counts: offsets[p] = sum_{q<p} counts[q] (device u64 [num_pixels+1],
  * offsets[num_pixels] = total).  workspace: >= 8 * (num_pixels / 1024 + 2) bytes.  Used to lay
  * out materialised per-pixel samples. */

@@ -34,6 +34,7 @@ from ._lib import (  # noqa: F401
     QMC_SAMPLER_XOR_TABLE,
     QMC_XOR_TABLE_CELLS,
     QMC_SHIFT_XOR,
+    QMC_STATIC_SCRATCH_BYTES,
     Integrand,
     QMCError,
     Sampler,
@@ -445,6 +446,25 @@ def qmc_integrate_pixels_l2_step(sampler, integrand, width, height, counts, targ
         _dev_ptr(counts, "counts", _u32_types()), _dev_ptr(target, "target", (torch.float32,)),
         _dev_ptr(means, "means", (torch.float32,)), _dev_ptr(loss, "loss", (torch.float32,)),
         _dev_ptr(grad_params, "grad_params", (torch.float32,)), _dev_ptr(workspace, "workspace"), workspace.numel()))
+    return means, loss, grad_params
+
+
+def qmc_integrate_pixels_l2_step_noalloc(sampler, integrand, width, height, counts, target, means, loss,
+                                         grad_params):
+    """The fused training step of qmc_integrate_pixels_l2_step without a workspace: the library's
+    static scratch on the device holds its work counter and accumulator, and nothing is allocated
+    (means, loss and grad_params are required; loss and grad_params are added into).  Calls that
+    overlap on one GPU share that scratch and must be ordered by the caller."""
+    torch = _torch()
+    P = width * height
+    _check_counts(counts, P, sampler)
+    if target.numel() != P or means.numel() != P:
+        raise ValueError("target and means must have width*height entries")
+    check(load().qmc_integrate_pixels_l2_step_noalloc(
+        context(counts.device), _stream(), ctypes.byref(sampler.c), ctypes.byref(integrand.c), width, height,
+        _dev_ptr(counts, "counts", _u32_types()), _dev_ptr(target, "target", (torch.float32,)),
+        _dev_ptr(means, "means", (torch.float32,)), _dev_ptr(loss, "loss", (torch.float32,)),
+        _dev_ptr(grad_params, "grad_params", (torch.float32,))))
     return means, loss, grad_params
 
 

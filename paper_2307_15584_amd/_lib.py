@@ -37,6 +37,7 @@ QMC_PIXEL_TABLE_SHIFT = 256
 QMC_XOR_TABLE_CELLS = 16384
 QMC_F_GENZ = 1
 QMC_F_LOBES = 2
+QMC_STATIC_SCRATCH_BYTES = 4 << 20
 
 
 class Sampler(ctypes.Structure):
@@ -87,6 +88,7 @@ SIGNATURES = {
                                             ctypes.c_size_t]),
     "qmc_integrate_pixels_l2_step": (_st, [_vp, _vp, _vp, _vp, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp,
                                            ctypes.c_size_t]),
+    "qmc_integrate_pixels_l2_step_noalloc": (_st, [_vp, _vp, _vp, _vp, _u32, _u32, _vp, _vp, _vp, _vp, _vp]),
     "qmc_sample_offsets": (_st, [_vp, _vp, _vp, _u32, _vp, _vp, ctypes.c_size_t]),
     "qmc_generate_pixel_samples": (_st, [_vp, _vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp, _u64, _vp,
                                          ctypes.c_size_t]),

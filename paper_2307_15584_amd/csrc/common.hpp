@@ -60,6 +60,7 @@ struct qmc_context_s {
     std::map<uint32_t, qmc::IntegrateTune> integrate_tunes;  // key: (kind, d, backward)
     hipStream_t capture_stream = nullptr;                    // private stream used only for graph capture
     std::vector<qmc::GraphEntry> graphs;
+    void* static_scratch = nullptr;  // device address of the library's static scratch on this device
 };
 
 namespace qmc {
@@ -97,6 +98,10 @@ inline qmc_status check_launch(const char* what) {
 }
 
 inline hipStream_t as_stream(qmc_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Device address of the static scratch of qmc_integrate_pixels_l2_step_noalloc on `device`, which
+// must be the current device; looked up once per device.
+qmc_status static_scratch_address(int device, void** ptr);
 
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 

@@ -17,10 +17,18 @@ extern "C" qmc_status qmc_create(int device, qmc_context* out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess)
         return qmc::fail(QMC_ERR_DEVICE, "qmc_create: hipGetDeviceProperties(%d) failed", device);
+    void* scratch = nullptr;
+    {
+        qmc::DeviceGuard guard(device);
+        if (guard.status != QMC_OK) return guard.status;
+        const qmc_status st = qmc::static_scratch_address(device, &scratch);
+        if (st != QMC_OK) return st;
+    }
     auto* ctx = new qmc_context_s();
     ctx->device = device;
     ctx->num_cus = prop.multiProcessorCount;
     ctx->max_threads_per_cu = prop.maxThreadsPerMultiProcessor;
+    ctx->static_scratch = scratch;
     *out = ctx;
     return QMC_OK;
 }

@@ -32,6 +32,7 @@
 // once to float.  Several copies of the words (by block) spread the atomics.
 // Results never depend on which wavefront ran which task, so they are bitwise reproducible.
 #include <cmath>
+#include <mutex>
 
 #include "common.hpp"
 #include "device_core.hpp"
@@ -1574,6 +1575,34 @@ qmc_status integrate_common(const char* who, qmc_context ctx, qmc_stream stream,
 }  // namespace
 }  // namespace qmc
 
+// Static scratch of qmc_integrate_pixels_l2_step_noalloc (work counter and exact accumulator):
+// every device the library runs on holds its own copy until the process ends.  Host code uses
+// the address that static_scratch_address() looked up on the device, never this name.
+static __device__ __align__(256) unsigned char scratch[QMC_STATIC_SCRATCH_BYTES];
+
+namespace qmc {
+
+qmc_status static_scratch_address(int device, void** ptr) {
+    static std::mutex mu;
+    static std::map<int, void*> addresses;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto it = addresses.find(device);
+    if (it != addresses.end()) {
+        *ptr = it->second;
+        return QMC_OK;
+    }
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(QMC_ERR_DEVICE, "qmc_create: no address for the static scratch on device %d: %s", device,
+                    hipGetErrorString(e));
+    addresses[device] = p;
+    *ptr = p;
+    return QMC_OK;
+}
+
+}  // namespace qmc
+
 using namespace qmc;
 
 extern "C" qmc_status qmc_workspace_size(qmc_context ctx, const qmc_sampler* sampler, const qmc_integrand* integrand,
@@ -1668,4 +1697,21 @@ extern "C" qmc_status qmc_generate_pixel_samples(qmc_context ctx, qmc_stream str
     else
         dispatch_sampler<SamplesFam<QMC_MAX_DIMS>>(sampler->kind, nus, shift, back, grid, hs, a);
     return check_launch(who);
+}
+
+extern "C" qmc_status qmc_integrate_pixels_l2_step_noalloc(qmc_context ctx, qmc_stream stream,
+                                                           const qmc_sampler* sampler, const qmc_integrand* integrand,
+                                                           uint32_t width, uint32_t height, const uint32_t* counts,
+                                                           const float* target, float* means, float* loss,
+                                                           float* grad_params) {
+    const char* who = "qmc_integrate_pixels_l2_step_noalloc";
+    if (!ctx || !sampler || !integrand || !loss)
+        return fail(QMC_ERR_INVALID_ARGUMENT, "%s: NULL context, sampler, integrand or loss", who);
+    if (!ctx->static_scratch) return fail(QMC_ERR_DEVICE, "%s: the context has no static scratch", who);
+    const size_t need = make_plan(integrand, width * height, 2).total;
+    if (need > QMC_STATIC_SCRATCH_BYTES)
+        return fail(QMC_ERR_WORKSPACE, "%s: the problem needs %zu bytes of scratch, the static scratch holds %u "
+                    "(at most 6552 parameters)", who, need, QMC_STATIC_SCRATCH_BYTES);
+    return integrate_common(who, ctx, stream, sampler, integrand, width, height, counts, 0u, 0xFFFFFFFFu, loss, means,
+                            target, grad_params, ctx->static_scratch, QMC_STATIC_SCRATCH_BYTES, 2);
 }
