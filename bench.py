@@ -56,105 +56,143 @@ def measured_traffic(algorithmic_bytes):
     return rec.get("hbm_bytes_per_launch")
 
 
-def _cpu_job(args):
-    lo, hi = args
-    import numpy as np  # noqa: F401
+_CPU_SETUP = {}
 
-    from oracle import digital, generate
-    from synth import cp_shifts, nus_seeds, sobol_direction_init
 
-    s = 32
-    mats = digital.sobol_matrices(s, sobol_direction_init(s, 0))
+def _cpu_setup(name):
+    """Per-process inputs of the oracle workloads (formed once per worker, outside the timing)."""
+    if name in _CPU_SETUP:
+        return _CPU_SETUP[name]
+    from oracle import digital, estimator
+    from synth import (counts_pow2, counts_progressive, counts_uniform, cp_shifts, genz_params, lattice_vector,
+                       lobe_params, nus_seeds, sobol_direction_init)
+
+    flags = estimator.PIXEL_NUS | estimator.PIXEL_SHIFT
+    if name == "gen":
+        v = (digital.sobol_matrices(32, sobol_direction_init(32, 0)), nus_seeds(32, 1), cp_shifts(32, 2),
+             lattice_vector(32, 20, 3))
+    elif name == "genz":
+        m8 = digital.sobol_matrices(8, sobol_direction_init(8, 0))
+        v = ({"kind": "sobol", "s": 8, "table": m8, "seed": 0xC3, "flags": flags},
+             {"kind": "genz", "d": 8, "pixel_params": genz_params(1920 * 1080, 4)}, counts_pow2(1920, 1080, 5))
+    elif name == "lobes":
+        m8 = digital.sobol_matrices(8, sobol_direction_init(8, 0))
+        v = ({"kind": "sobol", "s": 8, "table": m8, "seed": 0xC3, "flags": flags},
+             {"kind": "lobes", "d": 8, "num_lobes": 64, "params": lobe_params(64, 8, 6), "pixel_seed": 9},
+             counts_uniform(1920, 1080, 64))
+    else:  # progressive 3840x2160, d = 64, 32 lobes
+        m64 = digital.sobol_matrices(64, sobol_direction_init(64, 0))
+        v = ({"kind": "sobol", "s": 64, "table": m64, "seed": 0xC5, "flags": flags},
+             {"kind": "lobes", "d": 64, "num_lobes": 32, "params": lobe_params(32, 64, 6), "pixel_seed": 9},
+             counts_progressive(3840, 2160, 5, passes=16, spp_per_pass=64))
+    _CPU_SETUP[name] = v
+    return v
+
+
+def _cpu_task(job):
+    """One job of an oracle workload; returns (seconds, units of work done)."""
+    import numpy as np
+
+    from oracle import estimator, generate
+
+    kind = job[0]
+    if kind in ("sobol", "lattice"):
+        mats, seeds, shifts, g = _cpu_setup("gen")
+        lo, hi = job[1], job[2]
+        t0 = time.perf_counter()
+        if kind == "sobol":
+            generate.generate_sobol(mats, lo, hi - lo, seeds, shifts, 0)
+        else:
+            generate.generate_lattice(g, lo, hi - lo, shifts, 0)
+        return time.perf_counter() - t0, (hi - lo) * 32
+    W = 3840 if kind == "progressive" else 1920
+    y0, y1, x1 = job[1], job[2], job[3]
+    px = (np.arange(y0, y1)[:, None] * W + np.arange(x1)[None, :]).ravel()
+    sp, ig, counts = _cpu_setup("genz" if kind == "genz" else "progressive" if kind == "progressive" else "lobes")
+    samples = int(counts[px].astype(np.int64).sum())
     t0 = time.perf_counter()
-    generate.generate_sobol(mats, lo, hi - lo, nus_seeds(s, 1), cp_shifts(s, 2), 0)
-    return time.perf_counter() - t0
+    if kind == "lobes_fwd_bwd":
+        estimator.loss_and_gradient(sp, ig, counts, px, np.zeros(len(px)))
+    elif kind == "progressive":
+        for t in range(16):  # the 16 passes of 64 samples per pixel
+            estimator.integrate_pixels(sp, ig, counts, px, begin=64 * t, end=64 * t + 64)
+    else:
+        estimator.integrate_pixels(sp, ig, counts, px)
+    return time.perf_counter() - t0, samples
 
 
 def _cpu_model():
+    """Processor model(s) and the family/model/stepping numbers from /proc/cpuinfo."""
+    names, ids = set(), set()
     try:
         with open("/proc/cpuinfo") as fh:
-            for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+            cur = {}
+            for line in fh.read().split("\n") + [""]:
+                if not line.strip():
+                    if cur:
+                        names.add(cur.get("model name", "unknown"))
+                        ids.add("family %s model %s stepping %s" % (cur.get("cpu family", "?"), cur.get("model", "?"),
+                                                                    cur.get("stepping", "?")))
+                    cur = {}
+                    continue
+                k, _, v = line.partition(":")
+                cur[k.strip()] = v.strip()
     except OSError:
-        pass
-    return "unknown"
+        return "unknown"
+    return "; ".join(sorted(names)) + " (" + "; ".join(sorted(ids)) + ")"
 
 
-def cpu_baseline(points=1 << 23, chunks=128):
-    """The oracle on a bounded sample of the same workload (first `points` indices, 32 dims)."""
+def cpu_baseline():
+    """The oracle (NumPy, exact integers and FP64) on the host cores: the whole generation step
+    (scrambled Sobol' 2^24 x 32 and lattice 2^20 x 32) and crops of the pixel workloads, each
+    spread over a process pool (all-cores rate) and also reported per core (work / summed job
+    time).  The pool has at most 16 processes, the CPU share of one GPU on the benchmark hosts."""
     import multiprocessing as mp
 
     cores = min(os.cpu_count() or 1, 16)
-    step = points // chunks
-    jobs = [(k * step, (k + 1) * step) for k in range(chunks)]
     ctx = mp.get_context("spawn")
-    with ctx.Pool(cores) as pool:
-        pool.map(_cpu_job, [(0, 64)] * cores)  # import warm-up, untimed
-        t0 = time.perf_counter()
-        job_s = pool.map(_cpu_job, jobs)
-        wall = time.perf_counter() - t0
-    ptdims = points * 32
-    return {"value": ptdims / wall / 1e9, "unit": "Gpts·dim/s", "cores": cores, "kind": "oracle",
-            "value_1core": ptdims / sum(job_s) / 1e9, "cpu": _cpu_model(),
-            "sample": "first %d indices x 32 dims, scramble + rotation, u32 + float32; %.1f s wall on %d "
-                      "processes" % (points, wall, cores),
-            "pixels": cpu_pixel_oracle()}
-
-
-def cpu_pixel_oracle():
-    """The oracle's per-pixel estimator, one core, on crops of the pixel workloads (the crop's
-    pixels keep their full-image indices, seeds and counts)."""
-    import numpy as np
-
-    from oracle import digital, estimator
-    from synth import counts_pow2, counts_uniform, genz_params, lobe_params, sobol_direction_init
-
-    W, H = 1920, 1080
-    m8 = digital.sobol_matrices(8, sobol_direction_init(8, 0))
-    sp = {"kind": "sobol", "s": 8, "table": m8, "seed": 0xC3,
-          "flags": estimator.PIXEL_NUS | estimator.PIXEL_SHIFT}
-
-    def crop(n):
-        return (np.arange(n)[:, None] * W + np.arange(n)[None, :]).ravel()
-
+    plans = {
+        # name: (jobs, unit, description)
+        "sobol": ([("sobol", k << 17, (k + 1) << 17) for k in range(128)], "Gpts·dim/s",
+                  "scrambled Sobol' 2^24 x 32 (nested uniform scramble + rotation), u32 + float32"),
+        "lattice": ([("lattice", k << 16, (k + 1) << 16) for k in range(16)], "Gpts·dim/s",
+                    "rank-1 lattice 2^20 x 32 (rotation), u32 + float32"),
+        "genz": ([("genz", 16 * b, 16 * b + 16, 256) for b in range(16)], "pixel-samples/s",
+                 "Genz 1920x1080 with 2^k spp: the 256 x 256 top-left crop (its pixels' own seeds and counts)"),
+        "lobes_fwd": ([("lobes_fwd", 8 * b, 8 * b + 8, 128) for b in range(16)], "pixel-samples/s",
+                      "lobes 1920x1080 x 64 spp, d = 8, 64 lobes, forward: the 128 x 128 top-left crop"),
+        "lobes_fwd_bwd": ([("lobes_fwd_bwd", 3 * b, 3 * b + 3, 48) for b in range(16)], "pixel-samples/s",
+                          "the same, estimate + L2 loss + analytic gradient: the 48 x 48 top-left crop"),
+        "progressive_d64_fwd": ([("progressive", 4 * b, 4 * b + 4, 64) for b in range(16)], "pixel-samples/s",
+                                "3840x2160, d = 64, 32 lobes, counts in [64, 1024]: the 64 x 64 top-left crop "
+                                "through all 16 passes of 64 spp"),
+    }
     out = {}
-    c3 = counts_pow2(W, H, 5)
-    ig3 = {"kind": "genz", "d": 8, "pixel_params": genz_params(W * H, 4)}
-    px = crop(96)
-    t0 = time.perf_counter()
-    estimator.integrate_pixels(sp, ig3, c3, px)
-    dt = time.perf_counter() - t0
-    ns = int(c3[px].astype(np.int64).sum())
-    out["genz"] = {"pixel_samples_per_s": round(ns / dt, 1), "cores": 1, "crop": "96x96 pixels, %d samples" % ns}
-    c4 = counts_uniform(W, H, 64)
-    ig4 = {"kind": "lobes", "d": 8, "num_lobes": 64, "params": lobe_params(64, 8, 6), "pixel_seed": 9}
-    px = crop(48)
-    t0 = time.perf_counter()
-    estimator.integrate_pixels(sp, ig4, c4, px)
-    dt = time.perf_counter() - t0
-    out["lobes_fwd"] = {"pixel_samples_per_s": round(len(px) * 64 / dt, 1), "cores": 1,
-                        "crop": "48x48 pixels x 64 spp"}
-    px = crop(12)
-    t0 = time.perf_counter()
-    estimator.loss_and_gradient(sp, ig4, c4, px, np.zeros(len(px)))
-    dt = time.perf_counter() - t0
-    out["lobes_fwd_bwd"] = {"pixel_samples_per_s": round(len(px) * 64 / dt, 1), "cores": 1,
-                            "crop": "12x12 pixels x 64 spp (estimate, L2 loss and analytic gradient)"}
-    # one 64-spp pass of the 3840x2160 progressive run (d = 64, 32 lobes)
-    W5, H5 = 3840, 2160
-    m64 = digital.sobol_matrices(64, sobol_direction_init(64, 0))
-    sp5 = {"kind": "sobol", "s": 64, "table": m64, "seed": 0xC5,
-           "flags": estimator.PIXEL_NUS | estimator.PIXEL_SHIFT}
-    c5 = counts_uniform(W5, H5, 64)
-    ig5 = {"kind": "lobes", "d": 64, "num_lobes": 32, "params": lobe_params(32, 64, 6), "pixel_seed": 9}
-    px = (np.arange(16)[:, None] * W5 + np.arange(16)[None, :]).ravel()
-    t0 = time.perf_counter()
-    estimator.integrate_pixels(sp5, ig5, c5, px)
-    dt = time.perf_counter() - t0
-    out["progressive_d64_fwd"] = {"pixel_samples_per_s": round(len(px) * 64 / dt, 1), "cores": 1,
-                                  "crop": "16x16 pixels x 64 spp of the 3840x2160 run (one pass)"}
-    return out
+    with ctx.Pool(cores) as pool:
+        pool.map(_cpu_task, [("sobol", 0, 64)] * cores)  # imports, untimed
+        for name, (jobs, unit, what) in plans.items():
+            kinds = {"sobol": "gen", "lattice": "gen", "genz": "genz", "lobes_fwd": "lobes", "lobes_fwd_bwd": "lobes",
+                     "progressive_d64_fwd": "progressive"}
+            pool.map(_cpu_setup, [kinds[name]] * (4 * cores), chunksize=1)  # inputs, untimed
+            t0 = time.perf_counter()
+            res = pool.map(_cpu_task, jobs, chunksize=1)
+            wall = time.perf_counter() - t0
+            units = sum(r[1] for r in res)
+            busy = sum(r[0] for r in res)
+            scale = 1e9 if unit == "Gpts·dim/s" else 1.0
+            out[name] = {"value": round(units / wall / scale, 4 if scale > 1 else 1), "unit": unit,
+                         "value_1core": round(units / busy / scale, 4 if scale > 1 else 1),
+                         "work": units, "wall_s": round(wall, 2), "what": what}
+    crop = out["progressive_d64_fwd"]
+    crop["full_image_seconds_extrapolated"] = round(
+        float(_cpu_setup("progressive")[2].astype("int64").sum()) / crop["value"], 1)
+    crop["note"] = "full-image time extrapolated from the crop's all-cores rate"
+    gen_wall = out["sobol"]["wall_s"] + out["lattice"]["wall_s"]
+    ptdims = out["sobol"]["work"] + out["lattice"]["work"]
+    return {"value": round(ptdims / gen_wall / 1e9, 4), "unit": "Gpts·dim/s", "cores": cores, "kind": "oracle",
+            "sample": "the whole generation step (scrambled Sobol' 2^24 x 32 + lattice 2^20 x 32, u32 + float32) "
+                      "in %.1f s on %d processes" % (gen_wall, cores),
+            "host_logical_cpus": os.cpu_count(), "cpu": _cpu_model(), "workloads": out}
 
 
 def _timed(torch, fn, reps, warmup=1):
