@@ -308,10 +308,12 @@ typedef struct {
 
 /* Bytes of device workspace needed by qmc_integrate_pixels (backward = 0), by
  * qmc_integrate_pixels_backward (backward = 1) or by qmc_integrate_pixels_l2_step
- * (backward = 2) for this problem, in *bytes.  The workspace holds a work counter and, for
- * the adjoint, an exact accumulator of 640 bytes per gradient entry (n_theta entries, plus the
- * loss for the L2 step): 256 + 640 * n_row bytes, bounded by the parameter count and not by the
- * image size (2.6 MB for 4128 parameters).
+ * (backward = 2) for this problem, in *bytes.  The workspace holds 1024 bytes of task counters
+ * and, for the adjoint, an exact accumulator of 640 bytes per gradient entry (n_theta entries,
+ * plus the loss for the L2 step): 1024 + 640 * n_row bytes, bounded by the parameter count and
+ * not by the image size (2.6 MB for 4128 parameters); for the GENZ forward pass, the buckets
+ * that sort pixels with fewer than 64 samples by count and list the tiles with more: about
+ * 4 P + 20 T bytes for P pixels in T = ceil(P / 64) tiles (9 MB at 1920 x 1080).
  * Errors: INVALID_ARGUMENT (NULL), UNSUPPORTED (kind/dimension combination). */
 qmc_status qmc_workspace_size(qmc_context ctx, const qmc_sampler* sampler, const qmc_integrand* integrand,
                               uint32_t width, uint32_t height, int backward, size_t* bytes);
@@ -369,8 +371,8 @@ qmc_status qmc_integrate_pixels_l2_step(qmc_context ctx, qmc_stream stream, cons
  * argument: its work counter and exact accumulator live in the library's static scratch of
  * QMC_STATIC_SCRATCH_BYTES per device (held by every device the library runs on until the
  * process ends).  The call allocates nothing and launches kernels only.  Limit: the problem's
- * qmc_workspace_size(..., 2), 256 + 640 (L (2d+1) + 1) bytes, must not exceed
- * QMC_STATIC_SCRATCH_BYTES, i.e. L (2d+1) <= 6552 parameters; larger problems fail with
+ * qmc_workspace_size(..., 2), 1024 + 640 (L (2d+1) + 1) bytes, must not exceed
+ * QMC_STATIC_SCRATCH_BYTES, i.e. L (2d+1) <= 6550 parameters; larger problems fail with
  * WORKSPACE before anything is enqueued.  Every call on one device shares that device's scratch
  * and clears what it needs at its start, so calls that overlap on one GPU (other streams, other
  * threads, other contexts of the device) race and must be ordered by the caller.
@@ -391,7 +393,7 @@ qmc_status qmc_sample_offsets(qmc_context ctx, qmc_stream stream, const uint32_t
  * out[j * ld + offsets[p] + i] (float32), exactly the values the fused integration uses
  * (before any integrand offset).  sampler: SOBOL, LATTICE or XOR_TABLE.  offsets: from
  * qmc_sample_offsets; ld >= offsets[P]; out: device float32 [d][ld].
- * workspace: >= 256 bytes of device memory (a work counter). */
+ * workspace: >= 1024 bytes of device memory (work counters). */
 qmc_status qmc_generate_pixel_samples(qmc_context ctx, qmc_stream stream, const qmc_sampler* sampler, uint32_t d,
                                       uint32_t width, uint32_t height, const uint32_t* counts,
                                       const uint64_t* offsets, float* out, uint64_t ld, void* workspace,

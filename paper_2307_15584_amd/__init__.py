@@ -496,7 +496,7 @@ def qmc_generate_pixel_samples(sampler, d, width, height, counts, offsets, total
         raise TypeError("out must be a float32 tensor [d][ld]")
     if out.shape[0] < d or out.shape[1] < total:
         raise ValueError("out has shape %s; [>= %d][>= %d] needed" % (tuple(out.shape), d, total))
-    ws = _workspace(256, counts.device)
+    ws = _workspace(1024, counts.device)
     check(load().qmc_generate_pixel_samples(
         context(counts.device), _stream(), ctypes.byref(sampler.c), d, width, height,
         _dev_ptr(counts, "counts", _u32_types()), _dev_ptr(offsets, "offsets"), _dev_ptr(out, "out"),

@@ -12,14 +12,19 @@ namespace dev {
 
 __device__ __forceinline__ uint32_t brev(uint32_t x) { return __builtin_bitreverse32(x); }
 
-// Largest binary32 not above u * 2^-32 (never 1).  z leading zeros put the leading one of
-// u at bit 31 of (u << z); its top 24 bits (exactly representable) times 2^(-z-24) is the
-// truncated value.  u = 0 is computed as if u = 1 for the shift count and yields 0.
-__device__ __forceinline__ float u32_to_unifloat(uint32_t u) {
-    const uint32_t z = __builtin_clz(u | 1u);
-    const uint32_t m = (u << z) >> 8;
-    return __builtin_ldexpf(static_cast<float>(m), -static_cast<int>(z) - 24);
+// u * 2^-32 rounded down to binary32, times 2^32: u with every bit below its 24 leading
+// significant bits cleared, as a float (exact, at most 24 significant bits).  With z the count
+// of leading zeros, keep = 0xFFFFFF00 >> z selects bits 31-z .. 8-z; v_ffbh_u32 returns
+// 0xFFFFFFFF for u = 0 and the shift reads the low five bits of its count, so u = 0 gives
+// keep = 1 and the result 0.  Four VALU instructions (find-first-bit, shift, and, convert).
+__device__ __forceinline__ float u32_to_unifloat_x32(uint32_t u) {
+    uint32_t keep;
+    asm("v_ffbh_u32 %0, %1\n\tv_lshrrev_b32_e64 %0, %0, %2" : "=&v"(keep) : "v"(u), "s"(0xFFFFFF00u));
+    return static_cast<float>(u & keep);
 }
+
+// Largest binary32 not above u * 2^-32 (never 1): the value above scaled exactly by 2^-32.
+__device__ __forceinline__ float u32_to_unifloat(uint32_t u) { return u32_to_unifloat_x32(u) * 0x1p-32f; }
 
 // Switches this wavefront's FP32 rounding to round-toward-zero (MODE register, single-precision
 // round field = 3).  The mode is per-wavefront state initialised at wave launch, so it only

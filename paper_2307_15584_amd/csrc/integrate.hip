@@ -43,6 +43,9 @@ IntegrateTune& integrate_tune(qmc_context ctx, uint32_t fkind, uint32_t d, bool 
 
 namespace {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));  // four floats at any 4-byte boundary
+
 constexpr uint32_t kWave = 64;
 constexpr uint32_t kTile = 64;   // pixels per task
 constexpr uint32_t kQI = 26;     // stride entries for index bits 6..31
@@ -95,6 +98,14 @@ struct Args {
     uint32_t* queue;
     uint32_t dynamic;
     uint32_t total_waves;
+    // Genz buckets (see genz_bucket_count): totals [64] (entry 0: tiles with big pixels, entry n:
+    // pixels with n samples in the window), per-wave counts [64][bucket_waves], small-pixel list
+    // [P], list of tiles with big pixels [tiles]
+    uint32_t* bucket_total;
+    uint32_t* bucket_wave;
+    uint32_t* bucket_list;
+    uint32_t* big_tiles;
+    uint32_t bucket_waves;
     // adjoint: exact accumulators [kAccCopies][n_row][kAccWords], n_row = n_theta (+1 for the
     // loss sum of the L2 step)
     unsigned long long* acc;
@@ -183,11 +194,22 @@ __device__ __forceinline__ uint32_t packed_owner(uint32_t off, uint32_t g) {
     return q;
 }
 
+// Task queues: up to kQueues counters, kQueueStride words apart (separate cache lines).  With Q =
+// min(kQueues, blocks), block b takes tasks from queue q = b mod Q, which hands out q, q + Q,
+// q + 2Q, ...: same-address atomics serialise (about 11 ns each here), so one counter for all
+// wavefronts caps the task rate, while blocks are spread over the chip's eight dies in that same
+// rotation.  Every queue has at least one block, so every task is taken.
+constexpr uint32_t kQueues = 8;
+constexpr uint32_t kQueueStride = 32;
+constexpr size_t kQueueBytes = size_t(kQueues) * kQueueStride * 4;
+
 __device__ __forceinline__ uint32_t next_task(const Args& a, uint32_t wave_global, uint32_t iter) {
     if (a.dynamic) {
+        const uint32_t nq = min(kQueues, gridDim.x);
+        const uint32_t q = blockIdx.x % nq;
         uint32_t t = 0;
-        if (lane_id() == 0) t = atomicAdd(a.queue, 1u);
-        return __builtin_amdgcn_readfirstlane(t);
+        if (lane_id() == 0) t = atomicAdd(a.queue + q * kQueueStride, 1u);
+        return __builtin_amdgcn_readfirstlane(t) * nq + q;
     }
     return wave_global + iter * a.total_waves;
 }
@@ -655,17 +677,41 @@ __device__ __forceinline__ void acc_add(const Args& a, uint32_t e, float v) {
 }
 
 // ------------------------------------------------------------ Genz forward ----
-
+//
 // Genz product f(x) = exp(-sum_{j<4} a_j^2 (x_j - u_j)^2) * cos(2 pi u_4 + sum_{j>=4} a_j x_j),
 // evaluated as exp2(-sum (c_j (x_j - u_j))^2) with c_j = a_j sqrt(log2 e), and the phase in
 // turns, phi = u_4 + sum_{j>=4} (a_j / 2 pi) x_j, reduced to [-1/2, 1/2] before the hardware
-// cosine (which takes its argument in turns).
+// cosine (which takes its argument in turns).  Generated samples enter as X = x 2^32 (the float
+// before the final scaling of the conversion) with U = u 2^32, C = c 2^-32 and B = b 2^-32: every
+// operation then rounds exactly as it does on x (scaling by a power of two is exact), so the
+// result equals that of the materialised samples bit for bit, one multiply per dimension sooner.
+//
+// Work decomposition (one persistent launch after two small bucketing launches):
+//   * big pixels (at least 64 samples in the window): tasks are tiles of 64 pixels; the
+//     wavefront takes the tile's big pixels one at a time, lane l the samples l, l + 64, ...;
+//     the pixel's seeds, rotations and constants are wave-uniform (scalar registers), and the
+//     Sobol' index part is the round's base (uniform) XOR the lane's own C_j l (registers);
+//   * small pixels (1 to 63 samples): the bucketing launches list them by count (bucket n holds
+//     the pixels with n samples; buckets laid out from n = 63 down); a task is 64 pixels of one
+//     bucket, one per lane, every lane stepping through k = 0 .. n-1 together.  The index part
+//     C_j(begin + k) is then uniform (an LDS table of 64 rows), and a pixel's seeds, constants
+//     and sum stay in its lane's registers: no shuffles, no per-sample pixel bookkeeping.
+// Each pixel's sum is formed by one lane (small) or one fixed lane-and-reduction order (big),
+// so results do not depend on the order of a bucket or on the schedule.
+
 __device__ __forceinline__ float readlane_f(float v, uint32_t q) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
 }
 
+__device__ __forceinline__ uint32_t window_count(const Args& a, uint32_t N) {
+    const uint32_t hi = min(N, a.end);
+    return hi > a.begin ? hi - a.begin : 0u;
+}
+
+// Per-pixel constants; SCALED: for samples X = x 2^32 (see above).
 struct GenzPixel {
     float u[4], c[4], phi0, b[4];
+    template <bool SCALED>
     __device__ __forceinline__ void load(const Args& a, uint32_t p) {
         const float* pp = a.pixel_params + uint64_t(p) * 16;
         constexpr float kSqrtLog2e = 1.2011224087864498f;  // sqrt(log2(e))
@@ -675,6 +721,11 @@ struct GenzPixel {
             u[j] = pp[j];
             c[j] = pp[8 + j] * kSqrtLog2e;
             b[j] = pp[12 + j] * kInv2Pi;
+            if constexpr (SCALED) {
+                u[j] *= 0x1p32f;
+                c[j] *= 0x1p-32f;
+                b[j] *= 0x1p-32f;
+            }
         }
         phi0 = pp[4];
     }
@@ -705,68 +756,408 @@ struct GenzPixel {
     }
 };
 
+// Sampler state of one pixel (dimensions 0..7) for the Genz kernel: NUS seeds and their
+// multipliers, rotations, the lattice's Hilbert shift and generators, the XOR table sampler's
+// reorder entry and digit scrambles, or the materialised samples' offset.
+template <uint32_t SK, bool NUS, bool SHIFT>
+struct GenzSampler {
+    uint32_t seed[8], sm[8], shift[8];
+    uint32_t hs;
+    uint32_t gen[4][8];
+    uint32_t rc, scr[8];
+    uint64_t off;
+};
+
+// The state of pixel p formed by one lane (small pixels).
+template <uint32_t SK, bool NUS, bool SHIFT>
+__device__ __forceinline__ void genz_sampler_lane(GenzSampler<SK, NUS, SHIFT>& g, const SamplerLds<8>& S,
+                                                  const Args& a, uint32_t p) {
+#pragma unroll
+    for (uint32_t j = 0; j < 8; ++j) {
+        if constexpr (NUS) {
+            g.seed[j] = dev::pcg_hash(S.kn[j] ^ p);
+            g.sm[j] = dev::seed_multiplier(g.seed[j]);
+        }
+        if constexpr (SHIFT) g.shift[j] = pixel_rotation(a, S.kc[j], j, p);
+    }
+    if constexpr (SK == QMC_SAMPLER_LATTICE) {
+        g.hs = a.lhilbert ? pixel_hilbert_shift(a, p) : 0u;
+        if (a.lrgen) {
+#pragma unroll
+            for (uint32_t c = 0; c < 4; ++c)
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j) g.gen[c][j] = (c == 0 || a.linst4) ? pixel_generator(S.kn[j], p, c) : 0u;
+        }
+    }
+    if constexpr (SK == QMC_SAMPLER_XOR_TABLE) {
+        const uint32_t c = pixel_cell(a, p);
+        g.rc = a.xor_reorder[c];
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) g.scr[j] = a.xor_scramble[j * QMC_XOR_TABLE_CELLS + c];
+    }
+    if constexpr (SK == QMC_SAMPLER_POINTS) g.off = a.offsets[p];
+}
+
+// Randomisation and conversion of a generated component v of dimension j (X = x 2^32); SX:
+// rotation by XOR instead of addition.
+template <bool NUS, bool SHIFT, bool SX>
+__device__ __forceinline__ float genz_finish(uint32_t v, uint32_t seed, uint32_t sm, uint32_t shift) {
+    if constexpr (NUS) v = dev::nus_from_mirrored(v, seed, sm);
+    if constexpr (SHIFT) v = SX ? (v ^ shift) : (v + shift);
+    return dev::u32_to_unifloat_x32(v);
+}
+
+// Sample i = begin + k of a small pixel (k uniform over the wavefront): X = x 2^32 for generated
+// samples, x itself for materialised ones.  it: the LDS table of Sobol' index parts.
+template <uint32_t SK, bool NUS, bool SHIFT, bool BACK, bool SX, uint32_t INST>
+__device__ __forceinline__ void genz_sample_small(float (&X)[8], const GenzSampler<SK, NUS, SHIFT>& g,
+                                                  const SamplerLds<8>& S, const uint32_t (*it)[8], const Args& a,
+                                                  uint32_t k) {
+    const uint32_t i = a.begin + k;
+    if constexpr (SK == QMC_SAMPLER_SOBOL) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) X[j] = genz_finish<NUS, SHIFT, SX>(it[k][j], g.seed[j], g.sm[j], g.shift[j]);
+    } else if constexpr (SK == QMC_SAMPLER_LATTICE) {
+        const uint32_t il = a.linst4 ? (i >> 2) : i;
+        const uint32_t bi = dev::brev(BACK ? ~il : il) + g.hs;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t gj = a.lrgen ? g.gen[INST][j] : S.g[j];
+            X[j] = genz_finish<false, SHIFT, SX>(bi * gj, 0u, 0u, g.shift[j]);
+        }
+    } else if constexpr (SK == QMC_SAMPLER_XOR_TABLE) {
+        const uint32_t idx = (i ^ g.rc) & a.xor_mask;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            X[j] = dev::u32_to_unifloat_x32(a.table[uint64_t(j) * a.points_ld + idx] ^ g.scr[j]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) X[j] = a.points[uint64_t(j) * a.points_ld + g.off + i];
+    }
+}
+
+// Integrates the lane's small pixel p, which has n samples in the window (n uniform).
+template <uint32_t SK, bool NUS, bool SHIFT, bool BACK, bool SX>
+__device__ __forceinline__ float genz_small_pixel(const SamplerLds<8>& S, const uint32_t (*it)[8], const Args& a,
+                                                  uint32_t p, uint32_t n) {
+    constexpr bool kScaled = SK != QMC_SAMPLER_POINTS;
+    GenzPixel gp;
+    gp.load<kScaled>(a, p);
+    GenzSampler<SK, NUS, SHIFT> g;
+    genz_sampler_lane<SK, NUS, SHIFT>(g, S, a, p);
+    float acc = 0.0f;
+    if (SK == QMC_SAMPLER_LATTICE && a.lrgen && a.linst4) {
+        // four superimposed instances: sample i belongs to instance i mod 4 (uniform)
+        for (uint32_t k = 0; k < n; ++k) {
+            float X[8];
+            switch ((a.begin + k) & 3u) {
+                case 0: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 0>(X, g, S, it, a, k); break;
+                case 1: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 1>(X, g, S, it, a, k); break;
+                case 2: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 2>(X, g, S, it, a, k); break;
+                default: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 3>(X, g, S, it, a, k); break;
+            }
+            acc += gp.eval(X);
+        }
+    } else if constexpr (SK == QMC_SAMPLER_POINTS) {
+        // materialised samples: the pixel's next four samples of a dimension are consecutive, so
+        // one 16-byte load (4-byte alignment suffices) replaces four scattered 4-byte loads
+        const float* base = a.points + g.off + a.begin;
+        uint32_t k = 0;
+        for (; k + 4 <= n; k += 4) {
+            f32x4 v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = *reinterpret_cast<const f32x4_a4*>(base + uint64_t(j) * a.points_ld + k);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float X[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) X[j] = v[j][q];
+                acc += gp.eval(X);
+            }
+        }
+        for (; k < n; ++k) {
+            float X[8];
+            genz_sample_small<SK, NUS, SHIFT, BACK, SX, 0>(X, g, S, it, a, k);
+            acc += gp.eval(X);
+        }
+    } else {
+        for (uint32_t k = 0; k < n; ++k) {
+            float X[8];
+            genz_sample_small<SK, NUS, SHIFT, BACK, SX, 0>(X, g, S, it, a, k);
+            acc += gp.eval(X);
+        }
+    }
+    return acc;
+}
+
+// Integrates the big pixels of tile `task`.  lane_t: this lane's Sobol' index part C_j l
+// (mirrored when scrambling).
+template <uint32_t SK, bool NUS, bool SHIFT, bool BACK, bool SX>
+__device__ __forceinline__ void genz_big_tile(const SamplerLds<8>& S, const Args& a, uint32_t task,
+                                              const uint32_t (&lane_t)[8]) {
+    constexpr bool kScaled = SK != QMC_SAMPLER_POINTS;
+    const uint32_t lane = lane_id();
+    const uint32_t p = task * kTile + lane;
+    const bool inb = p < a.num_pixels;
+    const uint32_t N = inb ? a.counts[p] : 0u;
+    const uint32_t n = window_count(a, N);
+    uint64_t bigmask = __ballot(inb && n >= kWave);
+    GenzPixel own;
+    if (inb && n >= kWave) own.load<kScaled>(a, p);
+    uint32_t hs_own = 0;
+    if constexpr (SK == QMC_SAMPLER_LATTICE) {
+        if (a.lhilbert && inb && n >= kWave) hs_own = pixel_hilbert_shift(a, p);
+    }
+    // the lattice's instance of lane l's samples (i = begin + 64 r + l): the same in every round
+    const uint32_t inst = (SK == QMC_SAMPLER_LATTICE && a.linst4) ? ((a.begin + lane) & 3u) : 0u;
+    while (bigmask) {
+        const uint32_t q = __builtin_ctzll(bigmask);
+        bigmask &= bigmask - 1;
+        const uint32_t pp = task * kTile + q;
+        const uint32_t nn = __builtin_amdgcn_readlane(n, q);
+        const GenzPixel g = own.from_lane(q);
+        // Per-pixel values, one per lane, then uniform: lanes 0-7 the NUS seed of dimension
+        // lane, lanes 8-15 the rotation of dimension lane - 8; lanes 0-31 the random
+        // generators (instance lane / 8, dimension lane mod 8).
+        uint32_t hv = 0, gv = 0;
+        if (NUS && lane < 8) hv = dev::pcg_hash(S.kn[lane] ^ pp);
+        if (SHIFT && lane >= 8 && lane < 16) hv = pixel_rotation(a, S.kc[lane - 8], lane - 8, pp);
+        if constexpr (SK == QMC_SAMPLER_LATTICE) {
+            if (a.lrgen && lane < 32 && (a.linst4 || lane < 8)) gv = pixel_generator(S.kn[lane & 7], pp, lane >> 3);
+        }
+        uint32_t sd[8], sm[8], sh[8], gl[8], scr[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            sd[j] = __builtin_amdgcn_readlane(hv, j);
+            sm[j] = dev::seed_multiplier(sd[j]);
+            sh[j] = __builtin_amdgcn_readlane(hv, 8 + j);
+            if constexpr (SK == QMC_SAMPLER_LATTICE) gl[j] = a.lrgen ? __shfl(gv, inst * 8 + j, kWave) : S.g[j];
+        }
+        uint32_t hs = 0, rc = 0;
+        uint64_t off = 0;
+        if constexpr (SK == QMC_SAMPLER_LATTICE) hs = __builtin_amdgcn_readlane(hs_own, q);
+        if constexpr (SK == QMC_SAMPLER_XOR_TABLE) {
+            const uint32_t c = pixel_cell(a, pp);
+            rc = a.xor_reorder[c];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) scr[j] = a.xor_scramble[j * QMC_XOR_TABLE_CELLS + c];
+        }
+        if constexpr (SK == QMC_SAMPLER_POINTS) off = a.offsets[pp];
+        uint32_t base[8];  // Sobol': C_j(begin + 64 r) of the current round
+        if constexpr (SK == QMC_SAMPLER_SOBOL) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) base[j] = S.B0[j];
+        }
+        float acc = 0.0f;
+        const uint32_t rounds = (nn + kWave - 1) / kWave;
+        for (uint32_t r = 0; r < rounds; ++r) {
+            const uint32_t k = r * kWave + lane;
+            const uint32_t i = a.begin + k;
+            float X[8];
+            if constexpr (SK == QMC_SAMPLER_SOBOL) {
+                uint32_t v[8];
+                if (a.aligned) {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) v[j] = base[j] ^ lane_t[j];
+                } else {
+                    index_part<8, NUS>(v, S, a, i, 0u, nullptr, 0u);
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) X[j] = genz_finish<NUS, SHIFT, SX>(v[j], sd[j], sm[j], sh[j]);
+                if (a.aligned && r + 1 < rounds) {
+                    const uint32_t h = (a.begin >> 6) + r;
+                    const uint32_t t = min(static_cast<uint32_t>(__builtin_ctz(h + 1u)), kQI - 1);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) base[j] ^= S.Q[j][t];
+                }
+            } else if constexpr (SK == QMC_SAMPLER_LATTICE) {
+                const uint32_t il = a.linst4 ? (i >> 2) : i;
+                const uint32_t bi = dev::brev(BACK ? ~il : il) + hs;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) X[j] = genz_finish<false, SHIFT, SX>(bi * gl[j], 0u, 0u, sh[j]);
+            } else if constexpr (SK == QMC_SAMPLER_XOR_TABLE) {
+                const uint32_t idx = (i ^ rc) & a.xor_mask;
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    X[j] = dev::u32_to_unifloat_x32(a.table[uint64_t(j) * a.points_ld + idx] ^ scr[j]);
+            } else {
+                const bool valid = k < nn;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) X[j] = valid ? a.points[uint64_t(j) * a.points_ld + off + i] : 0.0f;
+            }
+            float f = g.eval(X);
+            if (k >= nn) f = 0.0f;
+            acc += f;
+        }
+        const float t = wave_sum_dpp(acc);
+        if (lane == 0) write_pixel_n(a, pp, t, a.counts[pp]);
+    }
+}
+
+// Bucketing, without atomics and in a fixed order.  Each bucketing wavefront covers 1024
+// consecutive pixels (16 tiles): bucket 0 counts its tiles that hold a big pixel, bucket n
+// (1 <= n < 64) its pixels with n samples in the window.  (1) genz_bucket_count writes each
+// wavefront's counts to bucket_wave[n][w]; (2) genz_bucket_scan turns each bucket's row into
+// exclusive prefix sums over the wavefronts and stores the bucket's total; (3) genz_bucket_fill
+// writes the tiles with big pixels to big_tiles and the small pixels to bucket_list, bucket n
+// starting at sum_{m > n} total[m], within a bucket by wavefront and then pixel order; it also
+// writes the results of pixels without samples in the window, which no task visits.
+constexpr uint32_t kBucketTiles = 16;  // tiles per bucketing wavefront
+
+// Calls visit(n, same, tile) for each distinct bucket among the lanes of one tile (pixel p =
+// tile * 64 + lane, n its window count): same = the lanes of small pixels with that count; big
+// = the tile holds a big pixel.
+template <typename F>
+__device__ __forceinline__ bool tile_buckets(const Args& a, uint32_t tile, uint32_t* n_out, F&& visit) {
+    const uint32_t p = tile * kTile + lane_id();
+    const uint32_t n = p < a.num_pixels ? window_count(a, a.counts[p]) : 0u;
+    *n_out = n;
+    bool pend = n >= 1 && n < kWave;
+    uint64_t mask = __ballot(pend);
+    while (mask) {
+        const uint32_t n0 = __builtin_amdgcn_readlane(n, __builtin_ctzll(mask));
+        const uint64_t same = __ballot(pend && n == n0);
+        visit(n0, same);
+        if (n == n0) pend = false;
+        mask &= ~same;
+    }
+    return __ballot(p < a.num_pixels && n >= kWave) != 0;
+}
+
+__global__ __launch_bounds__(256) void genz_bucket_count(Args a) {
+    const uint32_t lane = lane_id();
+    const uint32_t w = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (w >= a.bucket_waves) return;
+    uint32_t cnt = 0;  // lane n: this wavefront's count of bucket n
+    for (uint32_t r = 0; r < kBucketTiles; ++r) {
+        uint32_t n;
+        const bool big = tile_buckets(a, w * kBucketTiles + r, &n, [&](uint32_t n0, uint64_t same) {
+            if (lane == n0) cnt += static_cast<uint32_t>(__popcll(same));
+        });
+        if (big && lane == 0) ++cnt;
+    }
+    a.bucket_wave[uint64_t(lane) * a.bucket_waves + w] = cnt;
+}
+
+// One block per bucket: exclusive prefix sums of the bucket's per-wavefront counts, in place.
+__global__ __launch_bounds__(1024) void genz_bucket_scan(Args a) {
+    __shared__ uint32_t part[1024];
+    uint32_t* row = a.bucket_wave + uint64_t(blockIdx.x) * a.bucket_waves;
+    const uint32_t t = threadIdx.x;
+    const uint32_t per = (a.bucket_waves + 1023) / 1024;  // consecutive entries per thread
+    uint32_t sum = 0;
+    for (uint32_t k = 0; k < per; ++k) {
+        const uint32_t i = t * per + k;
+        if (i < a.bucket_waves) sum += row[i];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (uint32_t o = 1; o < 1024; o <<= 1) {
+        const uint32_t add = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+    for (uint32_t k = 0; k < per; ++k) {
+        const uint32_t i = t * per + k;
+        if (i < a.bucket_waves) {
+            const uint32_t v = row[i];
+            row[i] = run;
+            run += v;
+        }
+    }
+    if (t == 1023) a.bucket_total[blockIdx.x] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void genz_bucket_fill(Args a) {
+    const uint32_t lane = lane_id();
+    const uint32_t w = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (w >= a.bucket_waves) return;
+    // lane n: where this wavefront's entries of bucket n begin (list of small pixels: buckets from
+    // n = 63 down; list of tiles: bucket 0)
+    const uint32_t tot = lane >= 1 ? a.bucket_total[lane] : 0u;
+    uint32_t suffix = tot;  // sum_{m >= n} total[m]
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_down(suffix, o, kWave);
+        if (lane + o < 64) suffix += v;
+    }
+    const uint32_t above = suffix - tot;
+    uint32_t base = a.bucket_wave[uint64_t(lane) * a.bucket_waves + w] + (lane >= 1 ? above : 0u);
+    for (uint32_t r = 0; r < kBucketTiles; ++r) {
+        const uint32_t tile = w * kBucketTiles + r;
+        uint32_t n;
+        const bool big = tile_buckets(a, tile, &n, [&](uint32_t n0, uint64_t same) {
+            const uint32_t pos = __builtin_amdgcn_readlane(base, n0);
+            const uint32_t p = tile * kTile + lane;
+            if ((same >> lane) & 1u)
+                a.bucket_list[pos + static_cast<uint32_t>(__popcll(same & ((uint64_t(1) << lane) - 1u)))] = p;
+            if (lane == n0) base += static_cast<uint32_t>(__popcll(same));
+        });
+        if (big) {
+            if (lane == 0) a.big_tiles[base] = tile;
+            if (lane == 0) ++base;
+        }
+        const uint32_t p = tile * kTile + lane;
+        if (p < a.num_pixels && n == 0) write_pixel_n(a, p, 0.0f, a.counts[p]);
+    }
+}
+
 template <uint32_t SK, bool NUS, bool SHIFT, bool BACK>
 __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
-    constexpr int D = 8;
-    __shared__ SamplerLds<D> S;
-    __shared__ PixelLds<D> PXs[kWavesPerBlock];
-    __shared__ PackedSeeds<D> PKs[kWavesPerBlock];
-    stage_sampler<D, SK, NUS>(S, a);
+    __shared__ SamplerLds<8> S;
+    __shared__ alignas(16) uint32_t IT[kWave][8];  // small pixels, Sobol': C_j(begin + k), k < 64 (mirrored when scrambling)
+    stage_sampler<8, SK, NUS>(S, a);
+    if constexpr (SK == QMC_SAMPLER_SOBOL) {
+        for (uint32_t e = threadIdx.x; e < kWave * 8; e += blockDim.x) {
+            const uint32_t k = e >> 3, j = e & 7u, i = a.begin + k;
+            uint32_t x = 0;
+            for (uint32_t bt = 0; bt < 32; ++bt)
+                if ((i >> bt) & 1u) x ^= a.table[j * 32 + bt];
+            IT[k][j] = NUS ? dev::brev(x) : x;
+        }
+    }
     __syncthreads();
-    PixelLds<D>& PX = PXs[threadIdx.x >> 6];
-    PackedSeeds<D>* PK = (NUS || SHIFT || SK == QMC_SAMPLER_LATTICE) ? &PKs[threadIdx.x >> 6] : nullptr;
     const uint32_t lane = lane_id();
-    for_each_task(a, [&](uint32_t task) {
-        const TileInfo ti = tile_info(a, task);
-        float big_acc = 0.0f, small_acc = 0.0f;
-        GenzPixel gbig;
-        // Each lane loads its own pixel's parameters once per tile, so the loads of all 64
-        // pixels are in flight together; a big pixel takes its set from the owner lane
-        // (wave-uniform), a packed sample through a lane shuffle.
-        GenzPixel own;
-        if (ti.inb && ti.n) own.load(a, ti.p);
-        const uint32_t n_own = ti.inb ? a.counts[ti.p] : 0u;  // a big pixel's count, from its lane
-        walk_tile<D, SK, NUS, SHIFT, BACK, false>(
-            a, S, PX, task, ti.n, ti.inb, ti.off, ti.total,
-            [&](uint32_t q) {
-                big_acc = 0.0f;
-                gbig = own.from_lane(q);
-            },
-            [&](const float (&x)[D], uint32_t count, uint32_t q, uint32_t pp, bool is_big, uint32_t slot0, uint32_t) {
-                float f;
-                if (is_big) {
-                    f = gbig.eval(x);
-                } else {
-                    GenzPixel g;
+    uint32_t lane_t[8];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        g.u[j] = __shfl(own.u[j], q, kWave);
-                        g.c[j] = __shfl(own.c[j], q, kWave);
-                        g.b[j] = __shfl(own.b[j], q, kWave);
-                    }
-                    g.phi0 = __shfl(own.phi0, q, kWave);
-                    f = g.eval(x);
-                }
-                if (lane >= count) f = 0.0f;
-                if (is_big) {
-                    big_acc += f;
-                } else {
-                    // Sum each pixel's run within the round; the owner lane pulls the run's end.
-                    const float sc = segmented_scan(f, lane < count ? q : 0xFFFFFFFFu);
-                    const bool has = ti.ns > 0 && ti.off < slot0 + kWave && ti.off + ti.ns > slot0;
-                    const uint32_t e = has ? min(ti.off + ti.ns, slot0 + kWave) - 1 - slot0 : 0u;
-                    const float part = __shfl(sc, e, kWave);
-                    if (has) small_acc += part;
-                }
-            },
-            [&](uint32_t q) {
-                const float t = wave_sum_dpp(big_acc);
-                const uint32_t nq = __builtin_amdgcn_readlane(n_own, q);
-                if (lane == 0) write_pixel_n(a, task * kTile + q, t, nq);
-            },
-            PK);
-        if (ti.inb && ti.n < kWave) write_pixel_n(a, ti.p, small_acc, n_own);
-    });
+    for (int j = 0; j < 8; ++j) lane_t[j] = SK == QMC_SAMPLER_SOBOL ? S.T[j][lane] : 0u;
+    // Tasks: first the tiles that hold big pixels, then chunks of 64 small pixels.  Lane l
+    // describes bucket n = 63 - l (its size, first chunk, first list entry); small chunk c lies
+    // in the last bucket whose first chunk is <= c.
+    const uint32_t nbig = a.bucket_total[0];
+    const uint32_t h = lane < kWave - 1 ? a.bucket_total[kWave - 1 - lane] : 0u;
+    const uint32_t ch = (h + kWave - 1) / kWave;
+    uint32_t chunks, list_total;
+    const uint32_t cs = wave_excl_scan(ch, &chunks);
+    const uint32_t ls = wave_excl_scan(h, &list_total);
+    const uint32_t ntasks = nbig + chunks;
+    const uint32_t wave_global = blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint32_t iter = 0;; ++iter) {
+        const uint32_t t = next_task(a, wave_global, iter);
+        if (t >= ntasks) break;
+        if (t < nbig) {
+            const uint32_t tile = __builtin_amdgcn_readfirstlane(a.big_tiles[t]);
+            if (SHIFT && a.sxor)
+                genz_big_tile<SK, NUS, SHIFT, BACK, true>(S, a, tile, lane_t);
+            else
+                genz_big_tile<SK, NUS, SHIFT, BACK, false>(S, a, tile, lane_t);
+        } else {
+            const uint32_t c = t - nbig;
+            const uint64_t bm = __ballot(ch > 0 && cs <= c);
+            const uint32_t bl = 63u - static_cast<uint32_t>(__builtin_clzll(bm));
+            const uint32_t n = kWave - 1 - bl;
+            const uint32_t first = (c - __builtin_amdgcn_readlane(cs, bl)) * kWave;
+            const uint32_t hb = __builtin_amdgcn_readlane(h, bl);
+            if (first + lane < hb) {
+                const uint32_t p = a.bucket_list[__builtin_amdgcn_readlane(ls, bl) + first + lane];
+                const float s = (SHIFT && a.sxor) ? genz_small_pixel<SK, NUS, SHIFT, BACK, true>(S, IT, a, p, n)
+                                                  : genz_small_pixel<SK, NUS, SHIFT, BACK, false>(S, IT, a, p, n);
+                write_pixel_n(a, p, s, a.counts[p]);
+            }
+        }
+    }
 }
 
 // ----------------------------------------------------- lobes: shared layout ----
@@ -1212,7 +1603,9 @@ __global__ __launch_bounds__(256) void acc_finalize(const unsigned long long* __
     }
 }
 
-__global__ void reset_queue(uint32_t* q) { *q = 0u; }
+__global__ void reset_queue(uint32_t* q) {
+    if (threadIdx.x < kQueues) q[threadIdx.x * kQueueStride] = 0u;
+}
 
 // ------------------------------------------------ materialised samples (plain) ----
 
@@ -1295,10 +1688,13 @@ __global__ __launch_bounds__(256) void scan_add(uint64_t* __restrict__ offsets, 
 
 // -------------------------------------------------------------------- host ----
 
-// Workspace: the work counter (256 bytes), then for the adjoint the exact accumulator.
+// Workspace: the task queues (kQueueBytes), then for the adjoint the exact accumulator, or for the
+// Genz forward pass the buckets: totals (256 bytes), per-wavefront counts, the list of small
+// pixels and the list of tiles with big pixels.
 struct Plan {
-    size_t queue_off = 0, acc_off = 256, total = 256;
-    uint32_t num_tasks = 0, n_theta = 0, n_row = 0;
+    size_t queue_off = 0, acc_off = kQueueBytes, total_off = kQueueBytes, wave_off = kQueueBytes + 256, list_off = 0,
+           tiles_off = 0, total = kQueueBytes;
+    uint32_t num_tasks = 0, n_theta = 0, n_row = 0, bucket_waves = 0;
     uint64_t acc_words = 0;
 };
 
@@ -1311,6 +1707,12 @@ Plan make_plan(const qmc_integrand* ig, uint32_t P, int mode) {
     if (mode != 0) {
         pl.acc_words = uint64_t(kAccCopies) * pl.n_row * kAccWords;
         pl.total = pl.acc_off + pl.acc_words * 8;
+    } else if (ig && ig->kind == QMC_F_GENZ) {
+        auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+        pl.bucket_waves = (pl.num_tasks + kBucketTiles - 1) / kBucketTiles;
+        pl.list_off = pl.wave_off + up(size_t(kWave) * pl.bucket_waves * 4);
+        pl.tiles_off = pl.list_off + up(size_t(P) * 4);
+        pl.total = pl.tiles_off + up(size_t(pl.num_tasks) * 4);
     }
     return pl;
 }
@@ -1534,14 +1936,28 @@ qmc_status integrate_common(const char* who, qmc_context ctx, qmc_stream stream,
     a.acc = reinterpret_cast<unsigned long long*>(static_cast<char*>(ws) + pl.acc_off);
     a.n_theta = pl.n_theta;
     a.n_row = pl.n_row;
-    const uint32_t grid = persistent_grid(ctx, integrate_tune(ctx, ig->kind, ig->d, backward), pl.num_tasks, &a);
+    a.bucket_total = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.total_off);
+    a.bucket_wave = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.wave_off);
+    a.bucket_list = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.list_off);
+    a.big_tiles = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.tiles_off);
+    a.bucket_waves = pl.bucket_waves;
+    const bool genz = !backward && ig->kind == QMC_F_GENZ;
+    // the Genz pass runs a task per tile with big pixels and per 64 small pixels
+    const uint32_t grid = persistent_grid(ctx, integrate_tune(ctx, ig->kind, ig->d, backward),
+                                          genz ? 2 * pl.num_tasks : pl.num_tasks, &a);
     const bool nus = (sp->flags & QMC_PIXEL_NUS) != 0, shift = (sp->flags & QMC_PIXEL_SHIFT) != 0;
     const bool back = (sp->flags & QMC_LATTICE_BACKWARD) != 0;
     clear_launch_error();
-    if (a.dynamic) hipLaunchKernelGGL(reset_queue, dim3(1), dim3(1), 0, hs, a.queue);
+    if (a.dynamic) hipLaunchKernelGGL(reset_queue, dim3(1), dim3(kWave), 0, hs, a.queue);
     if (backward) {
         const uint32_t zb = static_cast<uint32_t>(std::min<uint64_t>((pl.acc_words + 255) / 256, 1024));
         hipLaunchKernelGGL(zero_words, dim3(zb), dim3(256), 0, hs, a.acc, pl.acc_words);
+    }
+    if (genz) {
+        const uint32_t bblocks = (pl.bucket_waves + kWavesPerBlock - 1) / kWavesPerBlock;
+        hipLaunchKernelGGL(genz_bucket_count, dim3(bblocks), dim3(256), 0, hs, a);
+        hipLaunchKernelGGL(genz_bucket_scan, dim3(kWave), dim3(1024), 0, hs, a);
+        hipLaunchKernelGGL(genz_bucket_fill, dim3(bblocks), dim3(256), 0, hs, a);
     }
     if (!backward) {
         if (ig->kind == QMC_F_GENZ)
@@ -1676,7 +2092,8 @@ extern "C" qmc_status qmc_generate_pixel_samples(qmc_context ctx, qmc_stream str
     if (st != QMC_OK) return st;
     if (uint64_t(width) * height == 0 || uint64_t(width) * height > 0xFFFFFFFFull - kTile)
         return fail(QMC_ERR_OUT_OF_RANGE, "%s: image size out of range", who);
-    if (!workspace || workspace_bytes < 256) return fail(QMC_ERR_WORKSPACE, "%s: 256 bytes of workspace needed", who);
+    if (!workspace || workspace_bytes < kQueueBytes)
+        return fail(QMC_ERR_WORKSPACE, "%s: %zu bytes of workspace needed", who, kQueueBytes);
     DeviceGuard guard(ctx->device);
     if (guard.status != QMC_OK) return guard.status;
     hipStream_t hs = as_stream(stream);
@@ -1691,7 +2108,7 @@ extern "C" qmc_status qmc_generate_pixel_samples(qmc_context ctx, qmc_stream str
     const bool nus = (sampler->flags & QMC_PIXEL_NUS) != 0, shift = (sampler->flags & QMC_PIXEL_SHIFT) != 0;
     const bool back = (sampler->flags & QMC_LATTICE_BACKWARD) != 0;
     clear_launch_error();
-    if (a.dynamic) hipLaunchKernelGGL(reset_queue, dim3(1), dim3(1), 0, hs, a.queue);
+    if (a.dynamic) hipLaunchKernelGGL(reset_queue, dim3(1), dim3(kWave), 0, hs, a.queue);
     if (d <= 8)
         dispatch_sampler<SamplesFam<8>>(sampler->kind, nus, shift, back, grid, hs, a);
     else
@@ -1711,7 +2128,7 @@ extern "C" qmc_status qmc_integrate_pixels_l2_step_noalloc(qmc_context ctx, qmc_
     const size_t need = make_plan(integrand, width * height, 2).total;
     if (need > QMC_STATIC_SCRATCH_BYTES)
         return fail(QMC_ERR_WORKSPACE, "%s: the problem needs %zu bytes of scratch, the static scratch holds %u "
-                    "(at most 6552 parameters)", who, need, QMC_STATIC_SCRATCH_BYTES);
+                    "(at most 6550 parameters)", who, need, QMC_STATIC_SCRATCH_BYTES);
     return integrate_common(who, ctx, stream, sampler, integrand, width, height, counts, 0u, 0xFFFFFFFFu, loss, means,
                             target, grad_params, ctx->static_scratch, QMC_STATIC_SCRATCH_BYTES, 2);
 }

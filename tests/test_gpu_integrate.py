@@ -605,6 +605,6 @@ def test_adjoint_workspace_is_bounded(qmc):
     for mode in (1, 2):
         n_row = 4128 + (mode == 2)
         for W, H in ((3840, 2160), (64, 1)):
-            assert qmc.qmc_workspace_size(ds, ig, W, H, mode) == 256 + 640 * n_row
+            assert qmc.qmc_workspace_size(ds, ig, W, H, mode) == 1024 + 640 * n_row
     ig8 = qmc.PixelIntegrand.lobes(torch.zeros(64 * 17, device="cuda"), 64, 8, 9)
-    assert qmc.qmc_workspace_size(ds, ig8, 1920, 1080, 1) == 256 + 640 * 1088
+    assert qmc.qmc_workspace_size(ds, ig8, 1920, 1080, 1) == 1024 + 640 * 1088

@@ -56,7 +56,7 @@ def test_noalloc_step_equals_workspace_step_twice(qmc):
 def test_noalloc_step_refuses_problems_beyond_the_scratch(qmc):
     import torch
 
-    W, H, L, d = 8, 8, 400, 8   # 400 x 17 = 6800 parameters > 6552
+    W, H, L, d = 8, 8, 400, 8   # 400 x 17 = 6800 parameters > 6550
     sp, ig, dc, target, n = _problem(qmc, d, L, W, H, 7)
     assert qmc.qmc_workspace_size(sp, ig, W, H, 2) > qmc.QMC_STATIC_SCRATCH_BYTES
     means = torch.empty(W * H, dtype=torch.float32, device="cuda")
@@ -65,7 +65,7 @@ def test_noalloc_step_refuses_problems_beyond_the_scratch(qmc):
     with pytest.raises(qmc.QMCError) as e:
         qmc.qmc_integrate_pixels_l2_step_noalloc(sp, ig, W, H, dc, target, means, loss, grad)
     assert e.value.status == 5 and "static scratch" in str(e.value)
-    # the largest problem that fits: 6552 parameters (L = 6552 / 17 rounded down: 385 lobes)
+    # the largest lobe count that fits at d = 8: 385 lobes (6545 parameters <= 6550)
     sp, ig, dc, target, n = _problem(qmc, 8, 385, W, H, 8)
     assert qmc.qmc_workspace_size(sp, ig, W, H, 2) <= qmc.QMC_STATIC_SCRATCH_BYTES
     ref = qmc.qmc_integrate_pixels_l2_step(sp, ig, W, H, dc, target)
