@@ -442,12 +442,50 @@ __global__ __launch_bounds__(kBlock) void lattice64_general(const uint32_t* __re
 // ------------------------------------------------------------ point-major ----
 //
 // out[(i - first) * ld + j]: a wavefront takes 64 consecutive points, forms up to 32
-// components of its lane's point into an LDS tile, then writes the tile row by row (two rows
-// of 128 bytes per store instruction), and repeats for the next 32 dimensions.  Blocks of four
+// components of its lane's point into an LDS tile, then writes the tile (eight rows of 128 bytes
+// per 16-byte store instruction when rows are 16-byte aligned, else two rows of 4-byte stores),
+// and repeats for the next 32 dimensions.  Blocks of four
 // wavefronts share the staged matrices, so the LDS a wavefront needs stays small and more of
 // them stream at once.
 
 constexpr uint32_t kPmWaves = 4;  // wavefronts per block
+
+// Writes the wavefront's tile (rows < rows, components j0 .. j0 + sg) to the outputs.  V16 (rows
+// of 16-byte aligned components, sg = 32): a lane stores components 4 (lane mod 8) .. + 3 of row
+// lane / 8 as one 16-byte store, eight rows per instruction; otherwise two rows of 4-byte stores.
+template <bool WU, bool WF, bool V16>
+__device__ __forceinline__ void store_tile(const uint32_t (&tile)[kWave][33], uint32_t lane, uint32_t rows,
+                                           uint32_t sg, uint32_t o0, uint32_t j0, uint32_t* __restrict__ ou,
+                                           float* __restrict__ of, uint64_t ld) {
+    if (V16 && sg == 32) {
+        const uint32_t c = (lane & 7u) * 4u;
+#pragma unroll 2
+        for (uint32_t r0 = 0; r0 < rows; r0 += 8) {
+            const uint32_t r = r0 + (lane >> 3);
+            if (r < rows) {
+                const u32x4 v{tile[r][c], tile[r][c + 1], tile[r][c + 2], tile[r][c + 3]};
+                const uint64_t at = uint64_t(o0 + r) * ld + j0 + c;
+                if constexpr (WU) *reinterpret_cast<u32x4*>(ou + at) = v;
+                if constexpr (WF)
+                    *reinterpret_cast<f32x4*>(of + at) =
+                        f32x4{dev::u32_to_unifloat_rtz(v.x), dev::u32_to_unifloat_rtz(v.y),
+                              dev::u32_to_unifloat_rtz(v.z), dev::u32_to_unifloat_rtz(v.w)};
+            }
+        }
+        return;
+    }
+    const uint32_t k32 = lane & 31u, sub = lane >> 5;
+#pragma unroll 4
+    for (uint32_t r0 = 0; r0 < rows; r0 += 2) {
+        const uint32_t r = r0 + sub;
+        if (k32 < sg && r < rows) {
+            const uint32_t v = tile[r][k32];
+            const uint64_t at = uint64_t(o0 + r) * ld + j0 + k32;
+            if constexpr (WU) ou[at] = v;
+            if constexpr (WF) of[at] = dev::u32_to_unifloat_rtz(v);
+        }
+    }
+}
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -460,7 +498,7 @@ __device__ __forceinline__ void wave_sync() {
 // reduction in DPP), and a part from the lane's six low bits, tabulated per dimension and lane
 // once per block; other starts use the plain matrix product.  SM: dimensions the block stages
 // (32 or 64).
-template <int SM, bool NUS, bool SHIFT, bool SXOR, bool WU, bool WF, bool SPLIT>
+template <int SM, bool NUS, bool SHIFT, bool SXOR, bool WU, bool WF, bool SPLIT, bool V16>
 __global__ __launch_bounds__(kWave * kPmWaves) void sobol_point_major(const uint32_t* __restrict__ mats, uint32_t s,
                                                                       uint32_t first, uint32_t n,
                                                                       const uint32_t* __restrict__ seeds,
@@ -519,18 +557,7 @@ __global__ __launch_bounds__(kWave * kPmWaves) void sobol_point_major(const uint
                 tile[lane][jj] = v;
             }
             wave_sync();
-            // two rows (points) per store instruction
-            const uint32_t sub = lane >> 5;
-#pragma unroll 4
-            for (uint32_t r0 = 0; r0 < rows; r0 += 2) {
-                const uint32_t r = r0 + sub;
-                if (k32 < sg && r < rows) {
-                    const uint32_t v = tile[r][k32];
-                    const uint64_t at = uint64_t(o0 + r) * ld + j0 + k32;
-                    if constexpr (WU) ou[at] = v;
-                    if constexpr (WF) of[at] = dev::u32_to_unifloat_rtz(v);
-                }
-            }
+            store_tile<WU, WF, V16>(tile, lane, rows, sg, o0, j0, ou, of, ld);
             wave_sync();
         }
     }
@@ -538,7 +565,7 @@ __global__ __launch_bounds__(kWave * kPmWaves) void sobol_point_major(const uint
 
 // Lattice points in the same tiles: a lane forms brev(i) once and multiplies it by each
 // component of the generator (Alg. 4).
-template <bool BACK, bool SHIFT, bool SXOR, bool WU, bool WF>
+template <bool BACK, bool SHIFT, bool SXOR, bool WU, bool WF, bool V16>
 __global__ __launch_bounds__(kWave * kPmWaves) void lattice_point_major(const uint32_t* __restrict__ gen, uint32_t s,
                                                                         uint32_t first, uint32_t n,
                                                                         const uint32_t* __restrict__ shifts,
@@ -564,17 +591,7 @@ __global__ __launch_bounds__(kWave * kPmWaves) void lattice_point_major(const ui
                 tile[lane][jj] = v;
             }
             wave_sync();
-            const uint32_t sub = lane >> 5;
-#pragma unroll 4
-            for (uint32_t r0 = 0; r0 < rows; r0 += 2) {
-                const uint32_t r = r0 + sub;
-                if (k32 < sg && r < rows) {
-                    const uint32_t v = tile[r][k32];
-                    const uint64_t at = uint64_t(o0 + r) * ld + j0 + k32;
-                    if constexpr (WU) ou[at] = v;
-                    if constexpr (WF) of[at] = dev::u32_to_unifloat_rtz(v);
-                }
-            }
+            store_tile<WU, WF, V16>(tile, lane, rows, sg, o0, j0, ou, of, ld);
             wave_sync();
         }
     }
@@ -1044,12 +1061,16 @@ extern "C" qmc_status qmc_generate_sobol(qmc_context ctx, qmc_stream stream, con
                     if (pm) {
                         const uint64_t want = (n + kWave * kPmWaves - 1) / (kWave * kPmWaves);
                         const uint32_t gx = static_cast<uint32_t>(std::min<uint64_t>(want, uint64_t(ctx->num_cus) * 8));
+                        const bool v16 = (ld % 4 == 0) && aligned16(out_u32) && aligned16(out_f32);
                         with_bool(first % kWave == 0, [&](auto SPLIT) {
                             auto go = [&](auto SMV) {
-                                hipLaunchKernelGGL((sobol_point_major<decltype(SMV)::value, NUS.value, SH.value, SX.value,
-                                                                     WU.value, WF.value, SPLIT.value>),
-                                                   dim3(gx), dim3(kWave * kPmWaves), 0, hs, matrices, s, first32, nn,
-                                                   nus_seeds, shifts, out_u32, out_f32, ld);
+                                with_bool(v16, [&](auto V16) {
+                                    hipLaunchKernelGGL((sobol_point_major<decltype(SMV)::value, NUS.value, SH.value,
+                                                                         SX.value, WU.value, WF.value, SPLIT.value,
+                                                                         V16.value>),
+                                                       dim3(gx), dim3(kWave * kPmWaves), 0, hs, matrices, s, first32,
+                                                       nn, nus_seeds, shifts, out_u32, out_f32, ld);
+                                });
                             };
                             if (s <= 32)
                                 go(std::integral_constant<int, 32>{});
@@ -1109,9 +1130,13 @@ extern "C" qmc_status qmc_generate_lattice(qmc_context ctx, qmc_stream stream, c
                     if (pm) {
                         const uint64_t want = (n + kWave * kPmWaves - 1) / (kWave * kPmWaves);
                         const uint32_t gx = static_cast<uint32_t>(std::min<uint64_t>(want, uint64_t(ctx->num_cus) * 8));
-                        hipLaunchKernelGGL((lattice_point_major<BK.value, SH.value, SX.value, WU.value, WF.value>),
-                                           dim3(gx), dim3(kWave * kPmWaves), 0, hs, generator, s, first32, nn, shifts,
-                                           out_u32, out_f32, ld);
+                        const bool v16 = (ld % 4 == 0) && aligned16(out_u32) && aligned16(out_f32);
+                        with_bool(v16, [&](auto V16) {
+                            hipLaunchKernelGGL(
+                                (lattice_point_major<BK.value, SH.value, SX.value, WU.value, WF.value, V16.value>),
+                                dim3(gx), dim3(kWave * kPmWaves), 0, hs, generator, s, first32, nn, shifts, out_u32,
+                                out_f32, ld);
+                        });
                     } else if (fast) {
                         with_bool(ctx->lattice_tune.nontemporal != 0, [&](auto NT) {
                             uint32_t nchunks;

@@ -237,6 +237,8 @@ def test_autotune_generate_reports_candidates(qmc):
     ("lattice", 32, 0, 5000, BACK, None),
     ("lattice", 5, 13, 777, XOR, 8),
     ("lattice", 40, 64 * 3, 3000, XOR, 41),     # two groups of dimensions
+    ("sobol", 40, 64 * 5, 2000, XOR, 44),       # 16-byte rows: vector stores, then a group of 8
+    ("lattice", 36, 0, 1500, XOR, 36),
 ])
 def test_point_major_layout(qmc, kind, s, first, n, flags, ld):
     """out[(i - first) * ld + j] against the oracle, bit for bit, and nothing written between
