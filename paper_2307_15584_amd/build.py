@@ -1,4 +1,5 @@
-"""Compile the HIP library libqmc.so for gfx950 in-tree (no JIT cache).
+"""Compile the HIP library libqmc.so for gfx950 in-tree (no JIT cache), and the VALU issue-rate
+probe (valu_rate) that measures the instruction rates behind the per-pixel kernels' roofline.
 
   python -m paper_2307_15584_amd.build
 """
@@ -15,6 +16,8 @@ INCLUDE = os.path.join(ROOT, "include")
 CSRC = os.path.join(PKG, "csrc")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libqmc.so")
+PROBE_SRC = os.path.join(CSRC, "probe", "valu_rate.cpp")
+PROBE = os.path.join(PKG, "valu_rate")
 
 SOURCES = ["context.hip", "setup.cpp", "generate.hip", "integrate.hip", "tune.hip"]
 
@@ -62,7 +65,21 @@ def build(verbose=False, jobs=None):
     if r.returncode != 0:
         raise RuntimeError("linking libqmc.so failed:\n%s\n%s" % (r.stdout, r.stderr))
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
+
+
+def build_probe(verbose=False):
+    """The standalone VALU issue-rate probe (an executable, not part of the library)."""
+    tmp = PROBE + ".tmp%d" % os.getpid()
+    cmd = [_hipcc()] + [f for f in FLAGS if f != "-fPIC"] + ["-x", "hip", PROBE_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("compiling valu_rate failed:\n%s\n%s" % (r.stdout, r.stderr))
+    os.replace(tmp, PROBE)
+    return PROBE
 
 
 if __name__ == "__main__":
