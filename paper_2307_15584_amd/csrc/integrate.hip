@@ -106,6 +106,8 @@ struct Args {
     uint32_t* bucket_list;
     uint32_t* big_tiles;
     uint32_t bucket_waves;
+    // Genz, Sobol' sampler: index-part tables (see genz_tables), read through the scalar cache
+    uint32_t* genz_tab;
     // adjoint: exact accumulators [kAccCopies][n_row][kAccWords], n_row = n_theta (+1 for the
     // loss sum of the L2 step)
     unsigned long long* acc;
@@ -756,6 +758,53 @@ struct GenzPixel {
     }
 };
 
+// Reads through the scalar cache: p must be the same in every lane.
+typedef const __attribute__((address_space(4))) uint32_t scalar_u32;
+__device__ __forceinline__ uint32_t sload(const uint32_t* p) { return *(const scalar_u32*)p; }
+
+// Sobol' tables of the Genz kernels, written before the integration launch (genz_tables):
+// IT[k][j] = C_j(begin + k) for k < 64, Q[t][j] = XOR of columns 6 .. 6 + t, B0[j] = C_j(begin),
+// T[l][j] = C_j l for l < 64; all mirrored when scrambling.  Word offsets:
+constexpr uint32_t kTabIT = 0, kTabQ = 512, kTabB0 = kTabQ + kQI * 8, kTabT = kTabB0 + 8,
+                   kTabWords = kTabT + 512;
+
+// Wave-uniform keys of the per-pixel hashes and the shared lattice generator (dimensions 0..7),
+// formed from the launch arguments in scalar registers; lane_kn / lane_kc: the keys of
+// dimension (lane mod 8), for the lanes that hash one dimension each.
+struct GenzKeys {
+    uint32_t kn[8], kc[8], g[8];
+    uint32_t lane_kn, lane_kc;
+    __device__ __forceinline__ void init(const Args& a) {
+        const uint32_t j8 = lane_id() & 7u;
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) {
+            kn[j] = dev::pcg_hash(a.seed + 2u * j);
+            kc[j] = dev::pcg_hash(a.seed + 2u * j + 1u);
+            g[j] = a.skind == QMC_SAMPLER_LATTICE ? sload(a.table + j) : 0u;
+        }
+        lane_kn = dev::pcg_hash(a.seed + 2u * j8);
+        lane_kc = dev::pcg_hash(a.seed + 2u * j8 + 1u);
+    }
+};
+
+// C_j i for dimensions 0..7 by the plain matrix product (mirrored when scrambling): windows that
+// do not start on a multiple of 64.
+template <bool NUS>
+__device__ __forceinline__ void sobol_index_direct(uint32_t (&v)[8], const Args& a, uint32_t i) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = 0u;
+    for (uint32_t b = 0; b < 32; ++b) {
+        if ((i >> b) & 1u) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] ^= a.table[j * 32 + b];
+        }
+    }
+    if constexpr (NUS) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = dev::brev(v[j]);
+    }
+}
+
 // Sampler state of one pixel (dimensions 0..7) for the Genz kernel: NUS seeds and their
 // multipliers, rotations, the lattice's Hilbert shift and generators, the XOR table sampler's
 // reorder entry and digit scrambles, or the materialised samples' offset.
@@ -770,15 +819,15 @@ struct GenzSampler {
 
 // The state of pixel p formed by one lane (small pixels).
 template <uint32_t SK, bool NUS, bool SHIFT>
-__device__ __forceinline__ void genz_sampler_lane(GenzSampler<SK, NUS, SHIFT>& g, const SamplerLds<8>& S,
-                                                  const Args& a, uint32_t p) {
+__device__ __forceinline__ void genz_sampler_lane(GenzSampler<SK, NUS, SHIFT>& g, const GenzKeys& K, const Args& a,
+                                                  uint32_t p) {
 #pragma unroll
     for (uint32_t j = 0; j < 8; ++j) {
         if constexpr (NUS) {
-            g.seed[j] = dev::pcg_hash(S.kn[j] ^ p);
+            g.seed[j] = dev::pcg_hash(K.kn[j] ^ p);
             g.sm[j] = dev::seed_multiplier(g.seed[j]);
         }
-        if constexpr (SHIFT) g.shift[j] = pixel_rotation(a, S.kc[j], j, p);
+        if constexpr (SHIFT) g.shift[j] = pixel_rotation(a, K.kc[j], j, p);
     }
     if constexpr (SK == QMC_SAMPLER_LATTICE) {
         g.hs = a.lhilbert ? pixel_hilbert_shift(a, p) : 0u;
@@ -786,7 +835,7 @@ __device__ __forceinline__ void genz_sampler_lane(GenzSampler<SK, NUS, SHIFT>& g
 #pragma unroll
             for (uint32_t c = 0; c < 4; ++c)
 #pragma unroll
-                for (uint32_t j = 0; j < 8; ++j) g.gen[c][j] = (c == 0 || a.linst4) ? pixel_generator(S.kn[j], p, c) : 0u;
+                for (uint32_t j = 0; j < 8; ++j) g.gen[c][j] = (c == 0 || a.linst4) ? pixel_generator(K.kn[j], p, c) : 0u;
         }
     }
     if constexpr (SK == QMC_SAMPLER_XOR_TABLE) {
@@ -808,21 +857,22 @@ __device__ __forceinline__ float genz_finish(uint32_t v, uint32_t seed, uint32_t
 }
 
 // Sample i = begin + k of a small pixel (k uniform over the wavefront): X = x 2^32 for generated
-// samples, x itself for materialised ones.  it: the LDS table of Sobol' index parts.
+// samples, x itself for materialised ones.  The Sobol' index parts C_j(begin + k) come from the
+// table through the scalar cache (one 32-byte scalar load per sample).
 template <uint32_t SK, bool NUS, bool SHIFT, bool BACK, bool SX, uint32_t INST>
 __device__ __forceinline__ void genz_sample_small(float (&X)[8], const GenzSampler<SK, NUS, SHIFT>& g,
-                                                  const SamplerLds<8>& S, const uint32_t (*it)[8], const Args& a,
-                                                  uint32_t k) {
+                                                  const GenzKeys& K, const Args& a, uint32_t k) {
     const uint32_t i = a.begin + k;
     if constexpr (SK == QMC_SAMPLER_SOBOL) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) X[j] = genz_finish<NUS, SHIFT, SX>(it[k][j], g.seed[j], g.sm[j], g.shift[j]);
+        for (int j = 0; j < 8; ++j)
+            X[j] = genz_finish<NUS, SHIFT, SX>(sload(a.genz_tab + kTabIT + k * 8 + j), g.seed[j], g.sm[j], g.shift[j]);
     } else if constexpr (SK == QMC_SAMPLER_LATTICE) {
         const uint32_t il = a.linst4 ? (i >> 2) : i;
         const uint32_t bi = dev::brev(BACK ? ~il : il) + g.hs;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const uint32_t gj = a.lrgen ? g.gen[INST][j] : S.g[j];
+            const uint32_t gj = a.lrgen ? g.gen[INST][j] : K.g[j];
             X[j] = genz_finish<false, SHIFT, SX>(bi * gj, 0u, 0u, g.shift[j]);
         }
     } else if constexpr (SK == QMC_SAMPLER_XOR_TABLE) {
@@ -838,23 +888,22 @@ __device__ __forceinline__ void genz_sample_small(float (&X)[8], const GenzSampl
 
 // Integrates the lane's small pixel p, which has n samples in the window (n uniform).
 template <uint32_t SK, bool NUS, bool SHIFT, bool BACK, bool SX>
-__device__ __forceinline__ float genz_small_pixel(const SamplerLds<8>& S, const uint32_t (*it)[8], const Args& a,
-                                                  uint32_t p, uint32_t n) {
+__device__ __forceinline__ float genz_small_pixel(const GenzKeys& K, const Args& a, uint32_t p, uint32_t n) {
     constexpr bool kScaled = SK != QMC_SAMPLER_POINTS;
     GenzPixel gp;
     gp.load<kScaled>(a, p);
     GenzSampler<SK, NUS, SHIFT> g;
-    genz_sampler_lane<SK, NUS, SHIFT>(g, S, a, p);
+    genz_sampler_lane<SK, NUS, SHIFT>(g, K, a, p);
     float acc = 0.0f;
     if (SK == QMC_SAMPLER_LATTICE && a.lrgen && a.linst4) {
         // four superimposed instances: sample i belongs to instance i mod 4 (uniform)
         for (uint32_t k = 0; k < n; ++k) {
             float X[8];
             switch ((a.begin + k) & 3u) {
-                case 0: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 0>(X, g, S, it, a, k); break;
-                case 1: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 1>(X, g, S, it, a, k); break;
-                case 2: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 2>(X, g, S, it, a, k); break;
-                default: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 3>(X, g, S, it, a, k); break;
+                case 0: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 0>(X, g, K, a, k); break;
+                case 1: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 1>(X, g, K, a, k); break;
+                case 2: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 2>(X, g, K, a, k); break;
+                default: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 3>(X, g, K, a, k); break;
             }
             acc += gp.eval(X);
         }
@@ -877,13 +926,13 @@ __device__ __forceinline__ float genz_small_pixel(const SamplerLds<8>& S, const 
         }
         for (; k < n; ++k) {
             float X[8];
-            genz_sample_small<SK, NUS, SHIFT, BACK, SX, 0>(X, g, S, it, a, k);
+            genz_sample_small<SK, NUS, SHIFT, BACK, SX, 0>(X, g, K, a, k);
             acc += gp.eval(X);
         }
     } else {
         for (uint32_t k = 0; k < n; ++k) {
             float X[8];
-            genz_sample_small<SK, NUS, SHIFT, BACK, SX, 0>(X, g, S, it, a, k);
+            genz_sample_small<SK, NUS, SHIFT, BACK, SX, 0>(X, g, K, a, k);
             acc += gp.eval(X);
         }
     }
@@ -893,7 +942,7 @@ __device__ __forceinline__ float genz_small_pixel(const SamplerLds<8>& S, const 
 // Integrates the big pixels of tile `task`.  lane_t: this lane's Sobol' index part C_j l
 // (mirrored when scrambling).
 template <uint32_t SK, bool NUS, bool SHIFT, bool BACK, bool SX>
-__device__ __forceinline__ void genz_big_tile(const SamplerLds<8>& S, const Args& a, uint32_t task,
+__device__ __forceinline__ void genz_big_tile(const GenzKeys& K, const Args& a, uint32_t task,
                                               const uint32_t (&lane_t)[8]) {
     constexpr bool kScaled = SK != QMC_SAMPLER_POINTS;
     const uint32_t lane = lane_id();
@@ -920,10 +969,10 @@ __device__ __forceinline__ void genz_big_tile(const SamplerLds<8>& S, const Args
         // lane, lanes 8-15 the rotation of dimension lane - 8; lanes 0-31 the random
         // generators (instance lane / 8, dimension lane mod 8).
         uint32_t hv = 0, gv = 0;
-        if (NUS && lane < 8) hv = dev::pcg_hash(S.kn[lane] ^ pp);
-        if (SHIFT && lane >= 8 && lane < 16) hv = pixel_rotation(a, S.kc[lane - 8], lane - 8, pp);
+        if (NUS && lane < 8) hv = dev::pcg_hash(K.lane_kn ^ pp);
+        if (SHIFT && lane >= 8 && lane < 16) hv = pixel_rotation(a, K.lane_kc, lane - 8, pp);
         if constexpr (SK == QMC_SAMPLER_LATTICE) {
-            if (a.lrgen && lane < 32 && (a.linst4 || lane < 8)) gv = pixel_generator(S.kn[lane & 7], pp, lane >> 3);
+            if (a.lrgen && lane < 32 && (a.linst4 || lane < 8)) gv = pixel_generator(K.lane_kn, pp, lane >> 3);
         }
         uint32_t sd[8], sm[8], sh[8], gl[8], scr[8];
 #pragma unroll
@@ -931,7 +980,7 @@ __device__ __forceinline__ void genz_big_tile(const SamplerLds<8>& S, const Args
             sd[j] = __builtin_amdgcn_readlane(hv, j);
             sm[j] = dev::seed_multiplier(sd[j]);
             sh[j] = __builtin_amdgcn_readlane(hv, 8 + j);
-            if constexpr (SK == QMC_SAMPLER_LATTICE) gl[j] = a.lrgen ? __shfl(gv, inst * 8 + j, kWave) : S.g[j];
+            if constexpr (SK == QMC_SAMPLER_LATTICE) gl[j] = a.lrgen ? __shfl(gv, inst * 8 + j, kWave) : K.g[j];
         }
         uint32_t hs = 0, rc = 0;
         uint64_t off = 0;
@@ -946,7 +995,7 @@ __device__ __forceinline__ void genz_big_tile(const SamplerLds<8>& S, const Args
         uint32_t base[8];  // Sobol': C_j(begin + 64 r) of the current round
         if constexpr (SK == QMC_SAMPLER_SOBOL) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) base[j] = S.B0[j];
+            for (int j = 0; j < 8; ++j) base[j] = sload(a.genz_tab + kTabB0 + j);
         }
         float acc = 0.0f;
         const uint32_t rounds = (nn + kWave - 1) / kWave;
@@ -960,7 +1009,7 @@ __device__ __forceinline__ void genz_big_tile(const SamplerLds<8>& S, const Args
 #pragma unroll
                     for (int j = 0; j < 8; ++j) v[j] = base[j] ^ lane_t[j];
                 } else {
-                    index_part<8, NUS>(v, S, a, i, 0u, nullptr, 0u);
+                    sobol_index_direct<NUS>(v, a, i);
                 }
 #pragma unroll
                 for (int j = 0; j < 8; ++j) X[j] = genz_finish<NUS, SHIFT, SX>(v[j], sd[j], sm[j], sh[j]);
@@ -968,7 +1017,7 @@ __device__ __forceinline__ void genz_big_tile(const SamplerLds<8>& S, const Args
                     const uint32_t h = (a.begin >> 6) + r;
                     const uint32_t t = min(static_cast<uint32_t>(__builtin_ctz(h + 1u)), kQI - 1);
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) base[j] ^= S.Q[j][t];
+                    for (int j = 0; j < 8; ++j) base[j] ^= sload(a.genz_tab + kTabQ + t * 8 + j);
                 }
             } else if constexpr (SK == QMC_SAMPLER_LATTICE) {
                 const uint32_t il = a.linst4 ? (i >> 2) : i;
@@ -1024,7 +1073,38 @@ __device__ __forceinline__ bool tile_buckets(const Args& a, uint32_t tile, uint3
     return __ballot(p < a.num_pixels && n >= kWave) != 0;
 }
 
+// The Sobol' tables of the Genz kernels (see kTabIT), by the first block of the bucketing launch.
+__device__ void genz_tables(const Args& a) {
+    const bool nus = (a.sflags & QMC_PIXEL_NUS) != 0;
+    for (uint32_t e = threadIdx.x; e < kTabWords; e += blockDim.x) {
+        uint32_t j, lo = 0, hi = 0, idx = 0;  // columns [lo, hi) of the index idx (all its bits when hi = 32)
+        if (e < kTabQ) {
+            j = e & 7u;
+            idx = a.begin + (e >> 3);
+            hi = 32;
+        } else if (e < kTabB0) {
+            j = (e - kTabQ) & 7u;
+            lo = 6;
+            hi = 7 + (e - kTabQ) / 8;
+            idx = 0xFFFFFFFFu;
+        } else if (e < kTabT) {
+            j = e - kTabB0;
+            idx = a.begin;
+            hi = 32;
+        } else {
+            j = (e - kTabT) & 7u;
+            idx = (e - kTabT) >> 3;
+            hi = 6;
+        }
+        uint32_t x = 0;
+        for (uint32_t b = lo; b < hi; ++b)
+            if ((idx >> b) & 1u) x ^= a.table[j * 32 + b];
+        a.genz_tab[e] = nus ? dev::brev(x) : x;
+    }
+}
+
 __global__ __launch_bounds__(256) void genz_bucket_count(Args a) {
+    if (blockIdx.x == 0 && a.skind == QMC_SAMPLER_SOBOL) genz_tables(a);
     const uint32_t lane = lane_id();
     const uint32_t w = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (w >= a.bucket_waves) return;
@@ -1106,23 +1186,12 @@ __global__ __launch_bounds__(256) void genz_bucket_fill(Args a) {
 
 template <uint32_t SK, bool NUS, bool SHIFT, bool BACK>
 __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
-    __shared__ SamplerLds<8> S;
-    __shared__ alignas(16) uint32_t IT[kWave][8];  // small pixels, Sobol': C_j(begin + k), k < 64 (mirrored when scrambling)
-    stage_sampler<8, SK, NUS>(S, a);
-    if constexpr (SK == QMC_SAMPLER_SOBOL) {
-        for (uint32_t e = threadIdx.x; e < kWave * 8; e += blockDim.x) {
-            const uint32_t k = e >> 3, j = e & 7u, i = a.begin + k;
-            uint32_t x = 0;
-            for (uint32_t bt = 0; bt < 32; ++bt)
-                if ((i >> bt) & 1u) x ^= a.table[j * 32 + bt];
-            IT[k][j] = NUS ? dev::brev(x) : x;
-        }
-    }
-    __syncthreads();
+    GenzKeys K;
+    K.init(a);
     const uint32_t lane = lane_id();
     uint32_t lane_t[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) lane_t[j] = SK == QMC_SAMPLER_SOBOL ? S.T[j][lane] : 0u;
+    for (int j = 0; j < 8; ++j) lane_t[j] = SK == QMC_SAMPLER_SOBOL ? a.genz_tab[kTabT + lane * 8 + j] : 0u;
     // Tasks: first the tiles that hold big pixels, then chunks of 64 small pixels.  Lane l
     // describes bucket n = 63 - l (its size, first chunk, first list entry); small chunk c lies
     // in the last bucket whose first chunk is <= c.
@@ -1140,9 +1209,9 @@ __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
         if (t < nbig) {
             const uint32_t tile = __builtin_amdgcn_readfirstlane(a.big_tiles[t]);
             if (SHIFT && a.sxor)
-                genz_big_tile<SK, NUS, SHIFT, BACK, true>(S, a, tile, lane_t);
+                genz_big_tile<SK, NUS, SHIFT, BACK, true>(K, a, tile, lane_t);
             else
-                genz_big_tile<SK, NUS, SHIFT, BACK, false>(S, a, tile, lane_t);
+                genz_big_tile<SK, NUS, SHIFT, BACK, false>(K, a, tile, lane_t);
         } else {
             const uint32_t c = t - nbig;
             const uint64_t bm = __ballot(ch > 0 && cs <= c);
@@ -1152,8 +1221,8 @@ __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
             const uint32_t hb = __builtin_amdgcn_readlane(h, bl);
             if (first + lane < hb) {
                 const uint32_t p = a.bucket_list[__builtin_amdgcn_readlane(ls, bl) + first + lane];
-                const float s = (SHIFT && a.sxor) ? genz_small_pixel<SK, NUS, SHIFT, BACK, true>(S, IT, a, p, n)
-                                                  : genz_small_pixel<SK, NUS, SHIFT, BACK, false>(S, IT, a, p, n);
+                const float s = (SHIFT && a.sxor) ? genz_small_pixel<SK, NUS, SHIFT, BACK, true>(K, a, p, n)
+                                                  : genz_small_pixel<SK, NUS, SHIFT, BACK, false>(K, a, p, n);
                 write_pixel_n(a, p, s, a.counts[p]);
             }
         }
@@ -1689,11 +1758,11 @@ __global__ __launch_bounds__(256) void scan_add(uint64_t* __restrict__ offsets, 
 // -------------------------------------------------------------------- host ----
 
 // Workspace: the task queues (kQueueBytes), then for the adjoint the exact accumulator, or for the
-// Genz forward pass the buckets: totals (256 bytes), per-wavefront counts, the list of small
-// pixels and the list of tiles with big pixels.
+// Genz forward pass the Sobol' tables (8 KB), the buckets' totals (256 bytes), per-wavefront
+// counts, the list of small pixels and the list of tiles with big pixels.
 struct Plan {
-    size_t queue_off = 0, acc_off = kQueueBytes, total_off = kQueueBytes, wave_off = kQueueBytes + 256, list_off = 0,
-           tiles_off = 0, total = kQueueBytes;
+    size_t queue_off = 0, acc_off = kQueueBytes, tab_off = kQueueBytes, total_off = kQueueBytes + 8192,
+           wave_off = kQueueBytes + 8192 + 256, list_off = 0, tiles_off = 0, total = kQueueBytes;
     uint32_t num_tasks = 0, n_theta = 0, n_row = 0, bucket_waves = 0;
     uint64_t acc_words = 0;
 };
@@ -1940,6 +2009,7 @@ qmc_status integrate_common(const char* who, qmc_context ctx, qmc_stream stream,
     a.bucket_wave = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.wave_off);
     a.bucket_list = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.list_off);
     a.big_tiles = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.tiles_off);
+    a.genz_tab = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.tab_off);
     a.bucket_waves = pl.bucket_waves;
     const bool genz = !backward && ig->kind == QMC_F_GENZ;
     // the Genz pass runs a task per tile with big pixels and per 64 small pixels

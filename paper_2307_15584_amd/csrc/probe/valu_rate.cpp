@@ -1,9 +1,10 @@
-// Issue rate of single VALU instructions on this GPU, in wave64 instructions per compute unit
-// per shader-clock cycle: the ceiling against which the per-pixel kernels' VALU roofline is
-// priced.  Every lane runs eight independent chains of one instruction (so dependences do not
-// limit issue).  One block per compute unit (its LDS request leaves room for no second block),
-// with the same number of wavefronts on each SIMD; each wavefront reads the shader clock
-// before and after its loop.
+// Issue rate of single VALU instructions on this GPU: the ceiling against which the per-pixel
+// kernels' VALU roofline is priced.  Every lane runs eight independent chains of one instruction
+// (so dependences do not limit issue).  One block per compute unit (its LDS request leaves room
+// for no second block), with the same number of wavefronts on each SIMD, and loops long enough
+// (a few milliseconds per launch) that launch and ramp-up do not matter.  Prints wave64
+// instructions per compute unit per nanosecond of wall time; divided by the shader clock
+// (GRBM_GUI_ACTIVE / 8 dies / duration under rocprofv3 --pmc) it is the rate per cycle.
 //
 //   valu_rate [waves_per_simd]     prints a markdown table
 #include <hip/hip_runtime.h>
@@ -23,7 +24,7 @@
         }                                                                                     \
     } while (0)
 
-constexpr int kIters = 512;   // loop trips
+constexpr int kIters = 8192;  // loop trips
 constexpr int kUnroll = 8;    // instructions per chain per trip
 constexpr int kChains = 8;    // independent chains per lane
 constexpr int kPerWave = kIters * kUnroll * kChains;
@@ -65,55 +66,47 @@ __device__ void CvtF32U32::run(uint32_t& r, uint32_t, uint32_t) { asm volatile("
 __device__ void ExpF32::run(uint32_t& r, uint32_t, uint32_t) { asm volatile("v_exp_f32 %0, %0" : "+v"(r)); }
 __device__ void CosF32::run(uint32_t& r, uint32_t, uint32_t) { asm volatile("v_cos_f32 %0, %0" : "+v"(r)); }
 
-// out[wave] = shader-clock cycles of the wave's loop; sink keeps the chains live.
+// sink keeps the chains live.
 template <typename Op>
-__global__ __launch_bounds__(1024) void issue(uint64_t* cycles, uint32_t* sink, uint32_t seed) {
+__global__ __launch_bounds__(1024) void issue(uint32_t* sink, uint32_t seed) {
     uint32_t r[kChains];
     const uint32_t a = seed | 1u, b = seed >> 3;
 #pragma unroll
     for (int c = 0; c < kChains; ++c) r[c] = threadIdx.x * 2654435761u + c;
     __syncthreads();
-    const uint64_t t0 = __builtin_amdgcn_s_memtime();
     for (int it = 0; it < kIters; ++it) {
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
             for (int c = 0; c < kChains; ++c) Op::run(r[c], a, b);
     }
-    const uint64_t t1 = __builtin_amdgcn_s_memtime();
     uint32_t x = 0;
 #pragma unroll
     for (int c = 0; c < kChains; ++c) x ^= r[c];
-    const uint32_t wave = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-    if ((threadIdx.x & 63) == 0) cycles[wave] = t1 - t0;
     if (x == 0x12345678u) sink[0] = x;
 }
 
 template <typename Op>
-void measure(int cus, int waves_per_simd, size_t lds, uint64_t* d_cycles, uint32_t* d_sink) {
+void measure(int cus, int waves_per_simd, size_t lds, uint32_t* d_sink) {
     const int blocks = cus;                  // one block per compute unit
     const int threads = 256 * waves_per_simd;  // waves_per_simd wavefronts on each of the 4 SIMDs
-    const int waves = blocks * 4 * waves_per_simd;
-    hipLaunchKernelGGL(issue<Op>, dim3(blocks), dim3(threads), lds, 0, d_cycles, d_sink, 12345u);  // warm-up
+    hipLaunchKernelGGL(issue<Op>, dim3(blocks), dim3(threads), lds, 0, d_sink, 12345u);  // warm-up
     CHECK(hipDeviceSynchronize());
     hipEvent_t e0, e1;
     CHECK(hipEventCreate(&e0));
     CHECK(hipEventCreate(&e1));
     CHECK(hipEventRecord(e0));
-    hipLaunchKernelGGL(issue<Op>, dim3(blocks), dim3(threads), lds, 0, d_cycles, d_sink, 777u);
+    hipLaunchKernelGGL(issue<Op>, dim3(blocks), dim3(threads), lds, 0, d_sink, 777u);
     CHECK(hipEventRecord(e1));
     CHECK(hipEventSynchronize(e1));
     CHECK(hipGetLastError());
     float ms = 0;
     CHECK(hipEventElapsedTime(&ms, e0, e1));
-    std::vector<uint64_t> c(waves);
-    CHECK(hipMemcpy(c.data(), d_cycles, waves * sizeof(uint64_t), hipMemcpyDeviceToHost));
-    std::sort(c.begin(), c.end());
-    const double med = static_cast<double>(c[waves / 2]);
-    // every CU runs 4 * waves_per_simd wavefronts concurrently, each issuing kPerWave instructions
-    const double per_cu_cycle = 4.0 * waves_per_simd * kPerWave / med;
-    const double clock_ghz = med / (ms * 1e6);
-    std::printf("| `%s` | %.2f | %.2f | %.3f |\n", Op::label, per_cu_cycle, clock_ghz, ms);
+    CHECK(hipEventDestroy(e0));
+    CHECK(hipEventDestroy(e1));
+    // every CU runs 4 * waves_per_simd wavefronts, each issuing kPerWave instructions
+    const double per_cu_ns = 4.0 * waves_per_simd * kPerWave / (ms * 1e6);
+    std::printf("| `%s` | %.3f | %.3f |\n", Op::label, per_cu_ns, ms);
 }
 
 int main(int argc, char** argv) {
@@ -126,29 +119,26 @@ int main(int argc, char** argv) {
         std::fprintf(stderr, "cannot request %zu bytes of LDS per block (at most %zu)\n", lds, prop.sharedMemPerBlock);
         return 1;
     }
-    uint64_t* d_cycles = nullptr;
     uint32_t* d_sink = nullptr;
-    CHECK(hipMalloc(&d_cycles, size_t(cus) * wps * 4 * sizeof(uint64_t)));
     CHECK(hipMalloc(&d_sink, 64));
     std::printf("%s, %d compute units, %d wavefronts per SIMD, %d instructions per wavefront, %zu B of LDS per "
                 "block\n\n", prop.gcnArchName, cus, wps, kPerWave, lds);
-    std::printf("| Instruction | wave64 instr / CU / cycle | clock (GHz, cycles / wall) | kernel ms |\n");
-    std::printf("|---|---:|---:|---:|\n");
-    measure<AddU32>(cus, wps, lds, d_cycles, d_sink);
-    measure<AddF32>(cus, wps, lds, d_cycles, d_sink);
-    measure<MulF32>(cus, wps, lds, d_cycles, d_sink);
-    measure<XorB32>(cus, wps, lds, d_cycles, d_sink);
-    measure<FmaF32>(cus, wps, lds, d_cycles, d_sink);
-    measure<FmacF32>(cus, wps, lds, d_cycles, d_sink);
-    measure<MadU24>(cus, wps, lds, d_cycles, d_sink);
-    measure<MulLoU32>(cus, wps, lds, d_cycles, d_sink);
-    measure<LshlB32>(cus, wps, lds, d_cycles, d_sink);
-    measure<BfrevB32>(cus, wps, lds, d_cycles, d_sink);
-    measure<FfbhU32>(cus, wps, lds, d_cycles, d_sink);
-    measure<CvtF32U32>(cus, wps, lds, d_cycles, d_sink);
-    measure<ExpF32>(cus, wps, lds, d_cycles, d_sink);
-    measure<CosF32>(cus, wps, lds, d_cycles, d_sink);
-    CHECK(hipFree(d_cycles));
+    std::printf("| Instruction | wave64 instr / CU / ns | kernel ms |\n");
+    std::printf("|---|---:|---:|\n");
+    measure<AddU32>(cus, wps, lds, d_sink);
+    measure<AddF32>(cus, wps, lds, d_sink);
+    measure<MulF32>(cus, wps, lds, d_sink);
+    measure<XorB32>(cus, wps, lds, d_sink);
+    measure<FmaF32>(cus, wps, lds, d_sink);
+    measure<FmacF32>(cus, wps, lds, d_sink);
+    measure<MadU24>(cus, wps, lds, d_sink);
+    measure<MulLoU32>(cus, wps, lds, d_sink);
+    measure<LshlB32>(cus, wps, lds, d_sink);
+    measure<BfrevB32>(cus, wps, lds, d_sink);
+    measure<FfbhU32>(cus, wps, lds, d_sink);
+    measure<CvtF32U32>(cus, wps, lds, d_sink);
+    measure<ExpF32>(cus, wps, lds, d_sink);
+    measure<CosF32>(cus, wps, lds, d_sink);
     CHECK(hipFree(d_sink));
     return 0;
 }

@@ -99,4 +99,4 @@ def test_workspace_sizes(driver_output):
     assert int(sizes["ws_lobes_bwd_bytes"]) == 1024 + 640 * 64 * 17
     assert int(sizes["ws_lobes_step_bytes"]) == 1024 + 640 * (64 * 17 + 1)
     P, T = 1920 * 1080, 1920 * 1080 // 64
-    assert 4 * P + 20 * T <= int(sizes["ws_genz_bytes"]) <= 4 * P + 20 * T + 2048
+    assert 4 * P + 20 * T <= int(sizes["ws_genz_bytes"]) <= 4 * P + 20 * T + 16384
