@@ -221,8 +221,9 @@ def _event_ms(torch, fn, reps):
 
 
 # ALU roofline of the fused pixel kernels.  One lane-op = one 32-bit VALU operation on one lane;
-# the peak is 256 CUs x 2.4 GHz x 2 wave64 instructions per CU per cycle = 78.6 T lane-ops/s
-# (FMA-class instructions alone issue at half that rate).
+# the peak is 256 CUs x 2.4 GHz x 2 wave64 instructions per CU per cycle = 78.6 T lane-ops/s.
+# Measured (valu_rate probe under counters): adds, multiplies, FMAs and logic sustain about 1.65
+# per CU per cycle, multiplies of integers, shifts and conversions 0.94, exp and cos 0.49.
 VALU_PEAK_T = 78.6
 GEN_OPS_PER_DIM = 20      # index part 1, nested scramble 11, rotation 1, conversion 7
 GENZ_EVAL_OPS = 21        # Gaussian 12, phase 4, range reduction 2, exp2 + cos + product 3

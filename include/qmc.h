@@ -311,9 +311,9 @@ typedef struct {
  * (backward = 2) for this problem, in *bytes.  The workspace holds 1024 bytes of task counters
  * and, for the adjoint, an exact accumulator of 640 bytes per gradient entry (n_theta entries,
  * plus the loss for the L2 step): 1024 + 640 * n_row bytes, bounded by the parameter count and
- * not by the image size (2.6 MB for 4128 parameters); for the GENZ forward pass, the buckets
- * that sort pixels with fewer than 64 samples by count and list the tiles with more: about
- * 4 P + 20 T bytes for P pixels in T = ceil(P / 64) tiles (9 MB at 1920 x 1080).
+ * not by the image size (2.6 MB for 4128 parameters); for the GENZ forward pass, the list of
+ * the P pixels sorted into buckets by sample count and the buckets' counts per 1024 pixels:
+ * about 4 P + 360 ceil(P / 1024) + 6144 bytes (9.0 MB at 1920 x 1080).
  * Errors: INVALID_ARGUMENT (NULL), UNSUPPORTED (kind/dimension combination). */
 qmc_status qmc_workspace_size(qmc_context ctx, const qmc_sampler* sampler, const qmc_integrand* integrand,
                               uint32_t width, uint32_t height, int backward, size_t* bytes);

@@ -45,6 +45,7 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));  // four floats at any 4-byte boundary
+typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
 
 constexpr uint32_t kWave = 64;
 constexpr uint32_t kTile = 64;   // pixels per task
@@ -98,13 +99,11 @@ struct Args {
     uint32_t* queue;
     uint32_t dynamic;
     uint32_t total_waves;
-    // Genz buckets (see genz_bucket_count): totals [64] (entry 0: tiles with big pixels, entry n:
-    // pixels with n samples in the window), per-wave counts [64][bucket_waves], small-pixel list
-    // [P], list of tiles with big pixels [tiles]
+    // Genz buckets (see genz_bucket_count): sizes [kBuckets], per-wavefront counts
+    // [kBuckets][bucket_waves], pixel list [P]
     uint32_t* bucket_total;
     uint32_t* bucket_wave;
     uint32_t* bucket_list;
-    uint32_t* big_tiles;
     uint32_t bucket_waves;
     // Genz, Sobol' sampler: index-part tables (see genz_tables), read through the scalar cache
     uint32_t* genz_tab;
@@ -246,8 +245,9 @@ struct PackedSeeds {
     uint32_t hshift[kWave];  // lattice: Hilbert shift of each pixel
 };
 
-// a + b as a separate add: keeps the compiler from contracting it with the product that formed
-// b into an FMA.  Plain FP32 adds and multiplies issue at twice the rate of FMAs on this chip.
+// a + b rounded as a separate add: keeps the compiler from contracting it with the product that
+// formed b into an FMA, so a sum rounds the same way in every kernel that forms it (the Genz
+// kernel's materialised-sample path must reproduce the generating paths bit for bit).
 __device__ __forceinline__ float add_nc(float a, float b) {
 #pragma clang fp contract(off)
     return a + b;
@@ -688,26 +688,27 @@ __device__ __forceinline__ void acc_add(const Args& a, uint32_t e, float v) {
 // operation then rounds exactly as it does on x (scaling by a power of two is exact), so the
 // result equals that of the materialised samples bit for bit, one multiply per dimension sooner.
 //
-// Work decomposition (one persistent launch after two small bucketing launches):
-//   * big pixels (at least 64 samples in the window): tasks are tiles of 64 pixels; the
-//     wavefront takes the tile's big pixels one at a time, lane l the samples l, l + 64, ...;
-//     the pixel's seeds, rotations and constants are wave-uniform (scalar registers), and the
-//     Sobol' index part is the round's base (uniform) XOR the lane's own C_j l (registers);
-//   * small pixels (1 to 63 samples): the bucketing launches list them by count (bucket n holds
-//     the pixels with n samples; buckets laid out from n = 63 down); a task is 64 pixels of one
-//     bucket, one per lane, every lane stepping through k = 0 .. n-1 together.  The index part
-//     C_j(begin + k) is then uniform (an LDS table of 64 rows), and a pixel's seeds, constants
-//     and sum stay in its lane's registers: no shuffles, no per-sample pixel bookkeeping.
-// Each pixel's sum is formed by one lane (small) or one fixed lane-and-reduction order (big),
-// so results do not depend on the order of a bucket or on the schedule.
-
-__device__ __forceinline__ float readlane_f(float v, uint32_t q) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
-}
+// Work decomposition: every pixel is integrated by one lane, which keeps the pixel's seeds,
+// rotations, constants and sum in registers.  Three small launches sort the pixels into buckets
+// (exact counts below 64, counts within a factor of two above), and a task is 64 pixels of one
+// bucket, one per lane, all lanes stepping through k = 0, 1, ... together (a lane adds only its
+// own n samples).  The sample index i = begin + k is then the same in every lane, so the Sobol'
+// index part C_j(i) = C_j(i - i mod 64) ^ C_j(i mod 64) comes from tables through the scalar
+// cache, updated once per 64 steps, and the lattice's phi_2(i) is a scalar value; only the
+// per-pixel scramble, rotation, conversion and the integrand remain per lane.  Each pixel's sum
+// is formed in sample order by one lane, so results depend neither on the order inside a bucket
+// nor on the schedule.
 
 __device__ __forceinline__ uint32_t window_count(const Args& a, uint32_t N) {
     const uint32_t hi = min(N, a.end);
     return hi > a.begin ? hi - a.begin : 0u;
+}
+
+// Bucket of a pixel with n >= 1 samples in the window: n itself below 64, else 64 + floor(log2(n /
+// 64)), so buckets 1 .. 89; tasks take the buckets from 89 down (the longest first).
+constexpr uint32_t kBuckets = 90;
+__device__ __forceinline__ uint32_t genz_bucket(uint32_t n) {
+    return n < kWave ? n : kWave + 31u - static_cast<uint32_t>(__builtin_clz(n >> 6));
 }
 
 // Per-pixel constants; SCALED: for samples X = x 2^32 (see above).
@@ -731,18 +732,6 @@ struct GenzPixel {
         }
         phi0 = pp[4];
     }
-    // The set held by lane q (wave-uniform result).
-    __device__ __forceinline__ GenzPixel from_lane(uint32_t q) const {
-        GenzPixel g;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            g.u[j] = readlane_f(u[j], q);
-            g.c[j] = readlane_f(c[j], q);
-            g.b[j] = readlane_f(b[j], q);
-        }
-        g.phi0 = readlane_f(phi0, q);
-        return g;
-    }
     __device__ __forceinline__ float eval(const float (&x)[8]) const {
         float e = 0.0f;
 #pragma unroll
@@ -762,50 +751,27 @@ struct GenzPixel {
 typedef const __attribute__((address_space(4))) uint32_t scalar_u32;
 __device__ __forceinline__ uint32_t sload(const uint32_t* p) { return *(const scalar_u32*)p; }
 
-// Sobol' tables of the Genz kernels, written before the integration launch (genz_tables):
-// IT[k][j] = C_j(begin + k) for k < 64, Q[t][j] = XOR of columns 6 .. 6 + t, B0[j] = C_j(begin),
-// T[l][j] = C_j l for l < 64; all mirrored when scrambling.  Word offsets:
-constexpr uint32_t kTabIT = 0, kTabQ = 512, kTabB0 = kTabQ + kQI * 8, kTabT = kTabB0 + 8,
-                   kTabWords = kTabT + 512;
+// Sobol' tables of the Genz kernel, written before the integration launch (genz_tables):
+// T[l][j] = C_j l for l < 64, Q[t][j] = XOR of columns 6 .. 6 + t (what C_j changes by when
+// index bits 6 .. 6 + t flip), H0[j] = C_j(begin - begin mod 64); mirrored when scrambling.
+// Word offsets:
+constexpr uint32_t kTabT = 0, kTabQ = 512, kTabH0 = kTabQ + kQI * 8, kTabWords = kTabH0 + 8;
 
 // Wave-uniform keys of the per-pixel hashes and the shared lattice generator (dimensions 0..7),
-// formed from the launch arguments in scalar registers; lane_kn / lane_kc: the keys of
-// dimension (lane mod 8), for the lanes that hash one dimension each.
+// formed from the launch arguments in scalar registers.
 struct GenzKeys {
     uint32_t kn[8], kc[8], g[8];
-    uint32_t lane_kn, lane_kc;
     __device__ __forceinline__ void init(const Args& a) {
-        const uint32_t j8 = lane_id() & 7u;
 #pragma unroll
         for (uint32_t j = 0; j < 8; ++j) {
             kn[j] = dev::pcg_hash(a.seed + 2u * j);
             kc[j] = dev::pcg_hash(a.seed + 2u * j + 1u);
             g[j] = a.skind == QMC_SAMPLER_LATTICE ? sload(a.table + j) : 0u;
         }
-        lane_kn = dev::pcg_hash(a.seed + 2u * j8);
-        lane_kc = dev::pcg_hash(a.seed + 2u * j8 + 1u);
     }
 };
 
-// C_j i for dimensions 0..7 by the plain matrix product (mirrored when scrambling): windows that
-// do not start on a multiple of 64.
-template <bool NUS>
-__device__ __forceinline__ void sobol_index_direct(uint32_t (&v)[8], const Args& a, uint32_t i) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = 0u;
-    for (uint32_t b = 0; b < 32; ++b) {
-        if ((i >> b) & 1u) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] ^= a.table[j * 32 + b];
-        }
-    }
-    if constexpr (NUS) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = dev::brev(v[j]);
-    }
-}
-
-// Sampler state of one pixel (dimensions 0..7) for the Genz kernel: NUS seeds and their
+// Sampler state of one pixel (dimensions 0..7), held by its lane: NUS seeds and their
 // multipliers, rotations, the lattice's Hilbert shift and generators, the XOR table sampler's
 // reorder entry and digit scrambles, or the materialised samples' offset.
 template <uint32_t SK, bool NUS, bool SHIFT>
@@ -815,40 +781,36 @@ struct GenzSampler {
     uint32_t gen[4][8];
     uint32_t rc, scr[8];
     uint64_t off;
+    __device__ __forceinline__ void init(const GenzKeys& K, const Args& a, uint32_t p) {
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) {
+            if constexpr (NUS) {
+                seed[j] = dev::pcg_hash(K.kn[j] ^ p);
+                sm[j] = dev::seed_multiplier(seed[j]);
+            }
+            if constexpr (SHIFT) shift[j] = pixel_rotation(a, K.kc[j], j, p);
+        }
+        if constexpr (SK == QMC_SAMPLER_LATTICE) {
+            hs = a.lhilbert ? pixel_hilbert_shift(a, p) : 0u;
+            if (a.lrgen) {
+#pragma unroll
+                for (uint32_t c = 0; c < 4; ++c)
+#pragma unroll
+                    for (uint32_t j = 0; j < 8; ++j) gen[c][j] = (c == 0 || a.linst4) ? pixel_generator(K.kn[j], p, c) : 0u;
+            }
+        }
+        if constexpr (SK == QMC_SAMPLER_XOR_TABLE) {
+            const uint32_t c = pixel_cell(a, p);
+            rc = a.xor_reorder[c];
+#pragma unroll
+            for (uint32_t j = 0; j < 8; ++j) scr[j] = a.xor_scramble[j * QMC_XOR_TABLE_CELLS + c];
+        }
+        if constexpr (SK == QMC_SAMPLER_POINTS) off = a.offsets[p];
+    }
 };
 
-// The state of pixel p formed by one lane (small pixels).
-template <uint32_t SK, bool NUS, bool SHIFT>
-__device__ __forceinline__ void genz_sampler_lane(GenzSampler<SK, NUS, SHIFT>& g, const GenzKeys& K, const Args& a,
-                                                  uint32_t p) {
-#pragma unroll
-    for (uint32_t j = 0; j < 8; ++j) {
-        if constexpr (NUS) {
-            g.seed[j] = dev::pcg_hash(K.kn[j] ^ p);
-            g.sm[j] = dev::seed_multiplier(g.seed[j]);
-        }
-        if constexpr (SHIFT) g.shift[j] = pixel_rotation(a, K.kc[j], j, p);
-    }
-    if constexpr (SK == QMC_SAMPLER_LATTICE) {
-        g.hs = a.lhilbert ? pixel_hilbert_shift(a, p) : 0u;
-        if (a.lrgen) {
-#pragma unroll
-            for (uint32_t c = 0; c < 4; ++c)
-#pragma unroll
-                for (uint32_t j = 0; j < 8; ++j) g.gen[c][j] = (c == 0 || a.linst4) ? pixel_generator(K.kn[j], p, c) : 0u;
-        }
-    }
-    if constexpr (SK == QMC_SAMPLER_XOR_TABLE) {
-        const uint32_t c = pixel_cell(a, p);
-        g.rc = a.xor_reorder[c];
-#pragma unroll
-        for (uint32_t j = 0; j < 8; ++j) g.scr[j] = a.xor_scramble[j * QMC_XOR_TABLE_CELLS + c];
-    }
-    if constexpr (SK == QMC_SAMPLER_POINTS) g.off = a.offsets[p];
-}
-
-// Randomisation and conversion of a generated component v of dimension j (X = x 2^32); SX:
-// rotation by XOR instead of addition.
+// Randomisation and conversion of a generated component v (X = x 2^32); SX: rotation by XOR
+// instead of addition.
 template <bool NUS, bool SHIFT, bool SX>
 __device__ __forceinline__ float genz_finish(uint32_t v, uint32_t seed, uint32_t sm, uint32_t shift) {
     if constexpr (NUS) v = dev::nus_from_mirrored(v, seed, sm);
@@ -856,17 +818,15 @@ __device__ __forceinline__ float genz_finish(uint32_t v, uint32_t seed, uint32_t
     return dev::u32_to_unifloat_x32(v);
 }
 
-// Sample i = begin + k of a small pixel (k uniform over the wavefront): X = x 2^32 for generated
-// samples, x itself for materialised ones.  The Sobol' index parts C_j(begin + k) come from the
-// table through the scalar cache (one 32-byte scalar load per sample).
+// Sample i = begin + k of the lane's pixel (k, i and ip uniform): X = x 2^32 for generated
+// samples, x itself for materialised ones.  ip: the Sobol' index parts C_j(i); lanes past
+// their own n (valid false) must not read materialised samples.
 template <uint32_t SK, bool NUS, bool SHIFT, bool BACK, bool SX, uint32_t INST>
-__device__ __forceinline__ void genz_sample_small(float (&X)[8], const GenzSampler<SK, NUS, SHIFT>& g,
-                                                  const GenzKeys& K, const Args& a, uint32_t k) {
-    const uint32_t i = a.begin + k;
+__device__ __forceinline__ void genz_sample(float (&X)[8], const GenzSampler<SK, NUS, SHIFT>& g, const GenzKeys& K,
+                                            const Args& a, uint32_t i, const uint32_t (&ip)[8], bool valid) {
     if constexpr (SK == QMC_SAMPLER_SOBOL) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            X[j] = genz_finish<NUS, SHIFT, SX>(sload(a.genz_tab + kTabIT + k * 8 + j), g.seed[j], g.sm[j], g.shift[j]);
+        for (int j = 0; j < 8; ++j) X[j] = genz_finish<NUS, SHIFT, SX>(ip[j], g.seed[j], g.sm[j], g.shift[j]);
     } else if constexpr (SK == QMC_SAMPLER_LATTICE) {
         const uint32_t il = a.linst4 ? (i >> 2) : i;
         const uint32_t bi = dev::brev(BACK ? ~il : il) + g.hs;
@@ -882,223 +842,202 @@ __device__ __forceinline__ void genz_sample_small(float (&X)[8], const GenzSampl
             X[j] = dev::u32_to_unifloat_x32(a.table[uint64_t(j) * a.points_ld + idx] ^ g.scr[j]);
     } else {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) X[j] = a.points[uint64_t(j) * a.points_ld + g.off + i];
+        for (int j = 0; j < 8; ++j) X[j] = valid ? a.points[uint64_t(j) * a.points_ld + g.off + i] : 0.0f;
     }
 }
 
-// Integrates the lane's small pixel p, which has n samples in the window (n uniform).
+// Integrates the lane's pixel p (n samples in the window) in a wavefront whose lanes step
+// through k < nmax together (nmax: the largest n of the task, uniform).
 template <uint32_t SK, bool NUS, bool SHIFT, bool BACK, bool SX>
-__device__ __forceinline__ float genz_small_pixel(const GenzKeys& K, const Args& a, uint32_t p, uint32_t n) {
+__device__ __forceinline__ float genz_pixel(const GenzKeys& K, const Args& a, uint32_t p, uint32_t n, uint32_t nmax) {
     constexpr bool kScaled = SK != QMC_SAMPLER_POINTS;
     GenzPixel gp;
     gp.load<kScaled>(a, p);
     GenzSampler<SK, NUS, SHIFT> g;
-    genz_sampler_lane<SK, NUS, SHIFT>(g, K, a, p);
+    g.init(K, a, p);
     float acc = 0.0f;
-    if (SK == QMC_SAMPLER_LATTICE && a.lrgen && a.linst4) {
-        // four superimposed instances: sample i belongs to instance i mod 4 (uniform)
-        for (uint32_t k = 0; k < n; ++k) {
-            float X[8];
-            switch ((a.begin + k) & 3u) {
-                case 0: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 0>(X, g, K, a, k); break;
-                case 1: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 1>(X, g, K, a, k); break;
-                case 2: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 2>(X, g, K, a, k); break;
-                default: genz_sample_small<SK, NUS, SHIFT, BACK, SX, 3>(X, g, K, a, k); break;
-            }
-            acc += gp.eval(X);
-        }
-    } else if constexpr (SK == QMC_SAMPLER_POINTS) {
-        // materialised samples: the pixel's next four samples of a dimension are consecutive, so
-        // one 16-byte load (4-byte alignment suffices) replaces four scattered 4-byte loads
+    if constexpr (SK == QMC_SAMPLER_POINTS) {
+        // Chunks of 32 samples, dimension by dimension: the lane reads 128 consecutive bytes of a
+        // dimension at a time (whole cache lines, not 16 bytes of 64 lines that must stay cached
+        // until the lane returns), keeping the exponent and phase sums of the chunk's samples.
+        // Per sample the operations and their order are those of GenzPixel::eval.
+        constexpr uint32_t kC = 32;
         const float* base = a.points + g.off + a.begin;
-        uint32_t k = 0;
-        for (; k + 4 <= n; k += 4) {
-            f32x4 v[8];
+        for (uint32_t k0 = 0; k0 < nmax; k0 += kC) {
+            if (k0 + kC <= n) {
+                float e[kC], ph[kC];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = *reinterpret_cast<const f32x4_a4*>(base + uint64_t(j) * a.points_ld + k);
+                for (uint32_t t = 0; t < kC; ++t) {
+                    e[t] = 0.0f;
+                    ph[t] = gp.phi0;
+                }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                float X[8];
+                for (int j = 0; j < 8; ++j) {
+                    const float* row = base + uint64_t(j) * a.points_ld + k0;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) X[j] = v[j][q];
-                acc += gp.eval(X);
+                    for (uint32_t q = 0; q < kC / 4; ++q) {
+                        const f32x4 v = *reinterpret_cast<const f32x4_a4*>(row + 4 * q);
+#pragma unroll
+                        for (uint32_t r = 0; r < 4; ++r) {
+                            const uint32_t t = 4 * q + r;
+                            if (j < 4) {
+                                const float d = gp.c[j] * (v[r] - gp.u[j]);
+                                e[t] = fmaf(d, d, e[t]);
+                            } else {
+                                ph[t] = fmaf(gp.b[j - 4], v[r], ph[t]);
+                            }
+                        }
+                    }
+                    // one dimension's loads in flight at a time
+                    asm volatile("" ::: "memory");
+                }
+#pragma unroll
+                for (uint32_t t = 0; t < kC; ++t) {
+                    const float w = ph[t] - rintf(ph[t]);
+                    acc = add_nc(acc, exp2_neg(e[t]) * __builtin_amdgcn_cosf(w));
+                }
+            } else {
+                // the pixel's last, partial chunk: sample by sample
+                for (uint32_t k = k0; k < n; ++k) {
+                    float X[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) X[j] = base[uint64_t(j) * a.points_ld + k];
+                    acc = add_nc(acc, gp.eval(X));
+                }
             }
         }
-        for (; k < n; ++k) {
+        return acc;
+    }
+    if constexpr (SK == QMC_SAMPLER_XOR_TABLE) {
+        // Samples i = begin + k in aligned groups of four: the table indices (i ^ rc) & mask of
+        // such a group are the four entries of one aligned group of four (N >= 4), entry t ^ (rc & 3)
+        // holding sample i + t, so one 16-byte load per dimension fetches them.  The values are
+        // summed in sample order.
+        uint32_t k = 0;
+        const auto single = [&](uint32_t kk) {
             float X[8];
-            genz_sample_small<SK, NUS, SHIFT, BACK, SX, 0>(X, g, K, a, k);
-            acc += gp.eval(X);
+            const uint32_t none[8] = {};
+            genz_sample<SK, NUS, SHIFT, BACK, SX, 0>(X, g, K, a, a.begin + kk, none, true);
+            const float f = gp.eval(X);
+            if (kk < n) acc = add_nc(acc, f);
+        };
+        if (a.xor_mask >= 3u) {
+            const uint32_t head = min(nmax, (4u - (a.begin & 3u)) & 3u);
+            for (; k < head; ++k) single(k);
+            const bool b0 = (g.rc & 1u) != 0, b1 = (g.rc & 2u) != 0;
+            for (; k + 4 <= nmax; k += 4) {
+                const uint32_t idx = ((a.begin + k) ^ g.rc) & a.xor_mask & ~3u;
+                u32x4_a4 w[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    w[j] = *reinterpret_cast<const u32x4_a4*>(a.table + uint64_t(j) * a.points_ld + idx);
+                float f[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float X[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) X[j] = dev::u32_to_unifloat_x32(w[j][r] ^ g.scr[j]);
+                    f[r] = gp.eval(X);
+                }
+                // s[t] = f[t ^ (rc & 3)]
+                const float g0 = b0 ? f[1] : f[0], g1 = b0 ? f[0] : f[1], g2 = b0 ? f[3] : f[2], g3 = b0 ? f[2] : f[3];
+                const float s0 = b1 ? g2 : g0, s1 = b1 ? g3 : g1, s2 = b1 ? g0 : g2, s3 = b1 ? g1 : g3;
+                if (k < n) acc = add_nc(acc, s0);
+                if (k + 1 < n) acc = add_nc(acc, s1);
+                if (k + 2 < n) acc = add_nc(acc, s2);
+                if (k + 3 < n) acc = add_nc(acc, s3);
+            }
         }
-    } else {
-        for (uint32_t k = 0; k < n; ++k) {
-            float X[8];
-            genz_sample_small<SK, NUS, SHIFT, BACK, SX, 0>(X, g, K, a, k);
-            acc += gp.eval(X);
+        for (; k < nmax; ++k) single(k);
+        return acc;
+    }
+    // Sobol' index part of step k: h = C_j(i - i mod 64) (uniform, advanced once per 64 indices)
+    // XOR T[i mod 64][j] (one scalar load of 32 bytes)
+    uint32_t h[8];
+    if constexpr (SK == QMC_SAMPLER_SOBOL) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) h[j] = sload(a.genz_tab + kTabH0 + j);
+    }
+    for (uint32_t k = 0; k < nmax; ++k) {
+        const uint32_t i = a.begin + k;
+        uint32_t ip[8];
+        if constexpr (SK == QMC_SAMPLER_SOBOL) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) ip[j] = h[j] ^ sload(a.genz_tab + kTabT + (i & 63u) * 8 + j);
+            if (((i + 1u) & 63u) == 0u) {
+                const uint32_t t = min(static_cast<uint32_t>(__builtin_ctz((i + 1u) >> 6)), kQI - 1);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) h[j] ^= sload(a.genz_tab + kTabQ + t * 8 + j);
+            }
         }
+        float X[8];
+        if (SK == QMC_SAMPLER_LATTICE && a.lrgen && a.linst4) {
+            // four superimposed instances: sample i belongs to instance i mod 4 (uniform)
+            switch (i & 3u) {
+                case 0: genz_sample<SK, NUS, SHIFT, BACK, SX, 0>(X, g, K, a, i, ip, true); break;
+                case 1: genz_sample<SK, NUS, SHIFT, BACK, SX, 1>(X, g, K, a, i, ip, true); break;
+                case 2: genz_sample<SK, NUS, SHIFT, BACK, SX, 2>(X, g, K, a, i, ip, true); break;
+                default: genz_sample<SK, NUS, SHIFT, BACK, SX, 3>(X, g, K, a, i, ip, true); break;
+            }
+        } else {
+            genz_sample<SK, NUS, SHIFT, BACK, SX, 0>(X, g, K, a, i, ip, true);
+        }
+        const float f = gp.eval(X);
+        if (k < n) acc = add_nc(acc, f);
     }
     return acc;
 }
 
-// Integrates the big pixels of tile `task`.  lane_t: this lane's Sobol' index part C_j l
-// (mirrored when scrambling).
-template <uint32_t SK, bool NUS, bool SHIFT, bool BACK, bool SX>
-__device__ __forceinline__ void genz_big_tile(const GenzKeys& K, const Args& a, uint32_t task,
-                                              const uint32_t (&lane_t)[8]) {
-    constexpr bool kScaled = SK != QMC_SAMPLER_POINTS;
-    const uint32_t lane = lane_id();
-    const uint32_t p = task * kTile + lane;
-    const bool inb = p < a.num_pixels;
-    const uint32_t N = inb ? a.counts[p] : 0u;
-    const uint32_t n = window_count(a, N);
-    uint64_t bigmask = __ballot(inb && n >= kWave);
-    GenzPixel own;
-    if (inb && n >= kWave) own.load<kScaled>(a, p);
-    uint32_t hs_own = 0;
-    if constexpr (SK == QMC_SAMPLER_LATTICE) {
-        if (a.lhilbert && inb && n >= kWave) hs_own = pixel_hilbert_shift(a, p);
-    }
-    // the lattice's instance of lane l's samples (i = begin + 64 r + l): the same in every round
-    const uint32_t inst = (SK == QMC_SAMPLER_LATTICE && a.linst4) ? ((a.begin + lane) & 3u) : 0u;
-    while (bigmask) {
-        const uint32_t q = __builtin_ctzll(bigmask);
-        bigmask &= bigmask - 1;
-        const uint32_t pp = task * kTile + q;
-        const uint32_t nn = __builtin_amdgcn_readlane(n, q);
-        const GenzPixel g = own.from_lane(q);
-        // Per-pixel values, one per lane, then uniform: lanes 0-7 the NUS seed of dimension
-        // lane, lanes 8-15 the rotation of dimension lane - 8; lanes 0-31 the random
-        // generators (instance lane / 8, dimension lane mod 8).
-        uint32_t hv = 0, gv = 0;
-        if (NUS && lane < 8) hv = dev::pcg_hash(K.lane_kn ^ pp);
-        if (SHIFT && lane >= 8 && lane < 16) hv = pixel_rotation(a, K.lane_kc, lane - 8, pp);
-        if constexpr (SK == QMC_SAMPLER_LATTICE) {
-            if (a.lrgen && lane < 32 && (a.linst4 || lane < 8)) gv = pixel_generator(K.lane_kn, pp, lane >> 3);
-        }
-        uint32_t sd[8], sm[8], sh[8], gl[8], scr[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            sd[j] = __builtin_amdgcn_readlane(hv, j);
-            sm[j] = dev::seed_multiplier(sd[j]);
-            sh[j] = __builtin_amdgcn_readlane(hv, 8 + j);
-            if constexpr (SK == QMC_SAMPLER_LATTICE) gl[j] = a.lrgen ? __shfl(gv, inst * 8 + j, kWave) : K.g[j];
-        }
-        uint32_t hs = 0, rc = 0;
-        uint64_t off = 0;
-        if constexpr (SK == QMC_SAMPLER_LATTICE) hs = __builtin_amdgcn_readlane(hs_own, q);
-        if constexpr (SK == QMC_SAMPLER_XOR_TABLE) {
-            const uint32_t c = pixel_cell(a, pp);
-            rc = a.xor_reorder[c];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) scr[j] = a.xor_scramble[j * QMC_XOR_TABLE_CELLS + c];
-        }
-        if constexpr (SK == QMC_SAMPLER_POINTS) off = a.offsets[pp];
-        uint32_t base[8];  // Sobol': C_j(begin + 64 r) of the current round
-        if constexpr (SK == QMC_SAMPLER_SOBOL) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) base[j] = sload(a.genz_tab + kTabB0 + j);
-        }
-        float acc = 0.0f;
-        const uint32_t rounds = (nn + kWave - 1) / kWave;
-        for (uint32_t r = 0; r < rounds; ++r) {
-            const uint32_t k = r * kWave + lane;
-            const uint32_t i = a.begin + k;
-            float X[8];
-            if constexpr (SK == QMC_SAMPLER_SOBOL) {
-                uint32_t v[8];
-                if (a.aligned) {
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) v[j] = base[j] ^ lane_t[j];
-                } else {
-                    sobol_index_direct<NUS>(v, a, i);
-                }
-#pragma unroll
-                for (int j = 0; j < 8; ++j) X[j] = genz_finish<NUS, SHIFT, SX>(v[j], sd[j], sm[j], sh[j]);
-                if (a.aligned && r + 1 < rounds) {
-                    const uint32_t h = (a.begin >> 6) + r;
-                    const uint32_t t = min(static_cast<uint32_t>(__builtin_ctz(h + 1u)), kQI - 1);
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) base[j] ^= sload(a.genz_tab + kTabQ + t * 8 + j);
-                }
-            } else if constexpr (SK == QMC_SAMPLER_LATTICE) {
-                const uint32_t il = a.linst4 ? (i >> 2) : i;
-                const uint32_t bi = dev::brev(BACK ? ~il : il) + hs;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) X[j] = genz_finish<false, SHIFT, SX>(bi * gl[j], 0u, 0u, sh[j]);
-            } else if constexpr (SK == QMC_SAMPLER_XOR_TABLE) {
-                const uint32_t idx = (i ^ rc) & a.xor_mask;
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    X[j] = dev::u32_to_unifloat_x32(a.table[uint64_t(j) * a.points_ld + idx] ^ scr[j]);
-            } else {
-                const bool valid = k < nn;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) X[j] = valid ? a.points[uint64_t(j) * a.points_ld + off + i] : 0.0f;
-            }
-            float f = g.eval(X);
-            if (k >= nn) f = 0.0f;
-            acc += f;
-        }
-        const float t = wave_sum_dpp(acc);
-        if (lane == 0) write_pixel_n(a, pp, t, a.counts[pp]);
-    }
-}
-
 // Bucketing, without atomics and in a fixed order.  Each bucketing wavefront covers 1024
-// consecutive pixels (16 tiles): bucket 0 counts its tiles that hold a big pixel, bucket n
-// (1 <= n < 64) its pixels with n samples in the window.  (1) genz_bucket_count writes each
-// wavefront's counts to bucket_wave[n][w]; (2) genz_bucket_scan turns each bucket's row into
-// exclusive prefix sums over the wavefronts and stores the bucket's total; (3) genz_bucket_fill
-// writes the tiles with big pixels to big_tiles and the small pixels to bucket_list, bucket n
-// starting at sum_{m > n} total[m], within a bucket by wavefront and then pixel order; it also
-// writes the results of pixels without samples in the window, which no task visits.
-constexpr uint32_t kBucketTiles = 16;  // tiles per bucketing wavefront
+// consecutive pixels.  (1) genz_bucket_count writes each wavefront's bucket sizes to
+// bucket_wave[b][w]; (2) genz_bucket_scan turns each bucket's row into exclusive prefix sums over
+// the wavefronts and stores the bucket's total; (3) genz_bucket_fill writes the pixels to
+// bucket_list, bucket b starting at sum_{b' > b} total[b'], within a bucket by wavefront and then
+// pixel order; it also writes the results of pixels without samples in the window, which no task
+// visits.  A lane keeps the values of buckets lane and lane + 64.
+constexpr uint32_t kBucketPixels = 1024;  // pixels per bucketing wavefront
 
-// Calls visit(n, same, tile) for each distinct bucket among the lanes of one tile (pixel p =
-// tile * 64 + lane, n its window count): same = the lanes of small pixels with that count; big
-// = the tile holds a big pixel.
+// Calls visit(b, same) for each distinct bucket b among the 64 pixels p0 + lane (same: the lanes
+// holding a pixel of bucket b).
 template <typename F>
-__device__ __forceinline__ bool tile_buckets(const Args& a, uint32_t tile, uint32_t* n_out, F&& visit) {
-    const uint32_t p = tile * kTile + lane_id();
+__device__ __forceinline__ void group_buckets(const Args& a, uint32_t p0, uint32_t* n_out, F&& visit) {
+    const uint32_t p = p0 + lane_id();
     const uint32_t n = p < a.num_pixels ? window_count(a, a.counts[p]) : 0u;
     *n_out = n;
-    bool pend = n >= 1 && n < kWave;
+    const uint32_t b = n ? genz_bucket(n) : 0u;
+    bool pend = n != 0;
     uint64_t mask = __ballot(pend);
     while (mask) {
-        const uint32_t n0 = __builtin_amdgcn_readlane(n, __builtin_ctzll(mask));
-        const uint64_t same = __ballot(pend && n == n0);
-        visit(n0, same);
-        if (n == n0) pend = false;
+        const uint32_t b0 = __builtin_amdgcn_readlane(b, __builtin_ctzll(mask));
+        const uint64_t same = __ballot(pend && b == b0);
+        visit(b0, same);
+        if (b == b0) pend = false;
         mask &= ~same;
     }
-    return __ballot(p < a.num_pixels && n >= kWave) != 0;
 }
 
-// The Sobol' tables of the Genz kernels (see kTabIT), by the first block of the bucketing launch.
+// The Sobol' tables of the Genz kernel (see kTabT), by the first block of the counting launch.
 __device__ void genz_tables(const Args& a) {
     const bool nus = (a.sflags & QMC_PIXEL_NUS) != 0;
     for (uint32_t e = threadIdx.x; e < kTabWords; e += blockDim.x) {
-        uint32_t j, lo = 0, hi = 0, idx = 0;  // columns [lo, hi) of the index idx (all its bits when hi = 32)
+        uint32_t j, lo = 0, hi, idx;  // columns [lo, hi) selected by the bits of idx
         if (e < kTabQ) {
             j = e & 7u;
-            idx = a.begin + (e >> 3);
-            hi = 32;
-        } else if (e < kTabB0) {
+            idx = e >> 3;
+            hi = 6;
+        } else if (e < kTabH0) {
             j = (e - kTabQ) & 7u;
             lo = 6;
             hi = 7 + (e - kTabQ) / 8;
             idx = 0xFFFFFFFFu;
-        } else if (e < kTabT) {
-            j = e - kTabB0;
-            idx = a.begin;
-            hi = 32;
         } else {
-            j = (e - kTabT) & 7u;
-            idx = (e - kTabT) >> 3;
-            hi = 6;
+            j = e - kTabH0;
+            idx = a.begin & ~63u;
+            hi = 32;
         }
         uint32_t x = 0;
-        for (uint32_t b = lo; b < hi; ++b)
-            if ((idx >> b) & 1u) x ^= a.table[j * 32 + b];
+        for (uint32_t bt = lo; bt < hi; ++bt)
+            if ((idx >> bt) & 1u) x ^= a.table[j * 32 + bt];
         a.genz_tab[e] = nus ? dev::brev(x) : x;
     }
 }
@@ -1108,15 +1047,21 @@ __global__ __launch_bounds__(256) void genz_bucket_count(Args a) {
     const uint32_t lane = lane_id();
     const uint32_t w = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (w >= a.bucket_waves) return;
-    uint32_t cnt = 0;  // lane n: this wavefront's count of bucket n
-    for (uint32_t r = 0; r < kBucketTiles; ++r) {
+    uint32_t cnt0 = 0, cnt1 = 0;  // buckets lane and lane + 64
+    for (uint32_t r = 0; r < kBucketPixels / kWave; ++r) {
         uint32_t n;
-        const bool big = tile_buckets(a, w * kBucketTiles + r, &n, [&](uint32_t n0, uint64_t same) {
-            if (lane == n0) cnt += static_cast<uint32_t>(__popcll(same));
+        group_buckets(a, w * kBucketPixels + r * kWave, &n, [&](uint32_t b0, uint64_t same) {
+            const uint32_t c = static_cast<uint32_t>(__popcll(same));
+            if (lane == (b0 & 63u)) {
+                if (b0 < kWave)
+                    cnt0 += c;
+                else
+                    cnt1 += c;
+            }
         });
-        if (big && lane == 0) ++cnt;
     }
-    a.bucket_wave[uint64_t(lane) * a.bucket_waves + w] = cnt;
+    a.bucket_wave[uint64_t(lane) * a.bucket_waves + w] = cnt0;
+    if (lane + kWave < kBuckets) a.bucket_wave[uint64_t(lane + kWave) * a.bucket_waves + w] = cnt1;
 }
 
 // One block per bucket: exclusive prefix sums of the bucket's per-wavefront counts, in place.
@@ -1150,81 +1095,106 @@ __global__ __launch_bounds__(1024) void genz_bucket_scan(Args a) {
     if (t == 1023) a.bucket_total[blockIdx.x] = part[1023];
 }
 
+// Inclusive suffix sum over the lanes (lane l receives sum_{m >= l} v_m).
+__device__ __forceinline__ uint32_t wave_suffix_sum(uint32_t v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_down(v, o, kWave);
+        if (lane + o < 64) v += u;
+    }
+    return v;
+}
+
 __global__ __launch_bounds__(256) void genz_bucket_fill(Args a) {
     const uint32_t lane = lane_id();
     const uint32_t w = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (w >= a.bucket_waves) return;
-    // lane n: where this wavefront's entries of bucket n begin (list of small pixels: buckets from
-    // n = 63 down; list of tiles: bucket 0)
-    const uint32_t tot = lane >= 1 ? a.bucket_total[lane] : 0u;
-    uint32_t suffix = tot;  // sum_{m >= n} total[m]
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t v = __shfl_down(suffix, o, kWave);
-        if (lane + o < 64) suffix += v;
-    }
-    const uint32_t above = suffix - tot;
-    uint32_t base = a.bucket_wave[uint64_t(lane) * a.bucket_waves + w] + (lane >= 1 ? above : 0u);
-    for (uint32_t r = 0; r < kBucketTiles; ++r) {
-        const uint32_t tile = w * kBucketTiles + r;
+    // where this wavefront's entries of buckets lane (base0) and lane + 64 (base1) begin
+    const uint32_t t0 = lane >= 1 ? a.bucket_total[lane] : 0u;
+    const uint32_t t1 = lane + kWave < kBuckets ? a.bucket_total[lane + kWave] : 0u;
+    const uint32_t s1 = wave_suffix_sum(t1);
+    const uint32_t all1 = __builtin_amdgcn_readfirstlane(s1);  // every bucket >= 64
+    const uint32_t s0 = wave_suffix_sum(t0);
+    uint32_t base0 = a.bucket_wave[uint64_t(lane) * a.bucket_waves + w] + (s0 - t0) + all1;
+    uint32_t base1 = lane + kWave < kBuckets ? a.bucket_wave[uint64_t(lane + kWave) * a.bucket_waves + w] + (s1 - t1)
+                                              : 0u;
+    for (uint32_t r = 0; r < kBucketPixels / kWave; ++r) {
+        const uint32_t p0 = w * kBucketPixels + r * kWave;
         uint32_t n;
-        const bool big = tile_buckets(a, tile, &n, [&](uint32_t n0, uint64_t same) {
-            const uint32_t pos = __builtin_amdgcn_readlane(base, n0);
-            const uint32_t p = tile * kTile + lane;
+        group_buckets(a, p0, &n, [&](uint32_t b0, uint64_t same) {
+            const uint32_t l0 = b0 & 63u;
+            const uint32_t pos = b0 < kWave ? __builtin_amdgcn_readlane(base0, l0) : __builtin_amdgcn_readlane(base1, l0);
             if ((same >> lane) & 1u)
-                a.bucket_list[pos + static_cast<uint32_t>(__popcll(same & ((uint64_t(1) << lane) - 1u)))] = p;
-            if (lane == n0) base += static_cast<uint32_t>(__popcll(same));
+                a.bucket_list[pos + static_cast<uint32_t>(__popcll(same & ((uint64_t(1) << lane) - 1u)))] = p0 + lane;
+            if (lane == l0) {
+                if (b0 < kWave)
+                    base0 += static_cast<uint32_t>(__popcll(same));
+                else
+                    base1 += static_cast<uint32_t>(__popcll(same));
+            }
         });
-        if (big) {
-            if (lane == 0) a.big_tiles[base] = tile;
-            if (lane == 0) ++base;
-        }
-        const uint32_t p = tile * kTile + lane;
+        const uint32_t p = p0 + lane;
         if (p < a.num_pixels && n == 0) write_pixel_n(a, p, 0.0f, a.counts[p]);
     }
 }
 
 template <uint32_t SK, bool NUS, bool SHIFT, bool BACK>
 __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
+    // Task table in processing order (position q holds bucket 89 - q): first chunk and first list
+    // entry of each bucket, and the bucket's size.
+    __shared__ uint32_t cs[kBuckets], ls[kBuckets], sz[kBuckets];
+    if (threadIdx.x < kWave) {
+        const uint32_t lane = threadIdx.x;
+        // lane l: positions l and l + 64 (buckets 89 - l and 25 - l)
+        const uint32_t h0 = a.bucket_total[kBuckets - 1 - lane];
+        const uint32_t h1 = lane + kWave < kBuckets - 1 ? a.bucket_total[kBuckets - 1 - kWave - lane] : 0u;
+        uint32_t c0tot, l0tot, dummy;
+        const uint32_t c0 = wave_excl_scan((h0 + kWave - 1) / kWave, &c0tot);
+        const uint32_t l0 = wave_excl_scan(h0, &l0tot);
+        const uint32_t c1 = wave_excl_scan((h1 + kWave - 1) / kWave, &dummy) + c0tot;
+        const uint32_t l1 = wave_excl_scan(h1, &dummy) + l0tot;
+        cs[lane] = c0;
+        ls[lane] = l0;
+        sz[lane] = h0;
+        if (lane + kWave < kBuckets) {
+            cs[lane + kWave] = c1;
+            ls[lane + kWave] = l1;
+            sz[lane + kWave] = h1;
+        }
+    }
+    __syncthreads();
     GenzKeys K;
     K.init(a);
     const uint32_t lane = lane_id();
-    uint32_t lane_t[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) lane_t[j] = SK == QMC_SAMPLER_SOBOL ? a.genz_tab[kTabT + lane * 8 + j] : 0u;
-    // Tasks: first the tiles that hold big pixels, then chunks of 64 small pixels.  Lane l
-    // describes bucket n = 63 - l (its size, first chunk, first list entry); small chunk c lies
-    // in the last bucket whose first chunk is <= c.
-    const uint32_t nbig = a.bucket_total[0];
-    const uint32_t h = lane < kWave - 1 ? a.bucket_total[kWave - 1 - lane] : 0u;
-    const uint32_t ch = (h + kWave - 1) / kWave;
-    uint32_t chunks, list_total;
-    const uint32_t cs = wave_excl_scan(ch, &chunks);
-    const uint32_t ls = wave_excl_scan(h, &list_total);
-    const uint32_t ntasks = nbig + chunks;
+    const uint32_t last = kBuckets - 2;  // position of bucket 1
+    const uint32_t ntasks = cs[last] + (sz[last] + kWave - 1) / kWave;
     const uint32_t wave_global = blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (uint32_t iter = 0;; ++iter) {
         const uint32_t t = next_task(a, wave_global, iter);
         if (t >= ntasks) break;
-        if (t < nbig) {
-            const uint32_t tile = __builtin_amdgcn_readfirstlane(a.big_tiles[t]);
-            if (SHIFT && a.sxor)
-                genz_big_tile<SK, NUS, SHIFT, BACK, true>(K, a, tile, lane_t);
-            else
-                genz_big_tile<SK, NUS, SHIFT, BACK, false>(K, a, tile, lane_t);
-        } else {
-            const uint32_t c = t - nbig;
-            const uint64_t bm = __ballot(ch > 0 && cs <= c);
-            const uint32_t bl = 63u - static_cast<uint32_t>(__builtin_clzll(bm));
-            const uint32_t n = kWave - 1 - bl;
-            const uint32_t first = (c - __builtin_amdgcn_readlane(cs, bl)) * kWave;
-            const uint32_t hb = __builtin_amdgcn_readlane(h, bl);
-            if (first + lane < hb) {
-                const uint32_t p = a.bucket_list[__builtin_amdgcn_readlane(ls, bl) + first + lane];
-                const float s = (SHIFT && a.sxor) ? genz_small_pixel<SK, NUS, SHIFT, BACK, true>(K, a, p, n)
-                                                  : genz_small_pixel<SK, NUS, SHIFT, BACK, false>(K, a, p, n);
-                write_pixel_n(a, p, s, a.counts[p]);
-            }
+        // the last position with cs <= t (positions of empty buckets share the next one's cs)
+        uint32_t q = 0;
+        for (uint32_t step = 64; step; step >>= 1)
+            if (q + step <= last && cs[q + step] <= t) q += step;
+        const uint32_t first = (t - cs[q]) * kWave;
+        const bool valid = first + lane < sz[q];
+        const uint32_t p = valid ? a.bucket_list[ls[q] + first + lane] : 0u;
+        const uint32_t N = valid ? a.counts[p] : 0u;
+        const uint32_t n = valid ? window_count(a, N) : 0u;
+        const uint32_t b = kBuckets - 1 - q;
+        // exact counts below 64; above, the task steps to its largest count
+        uint32_t nmax = b;
+        if (b >= kWave) {
+            uint32_t m = n;
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) m = max(m, static_cast<uint32_t>(__shfl_xor(m, o, kWave)));
+            nmax = __builtin_amdgcn_readfirstlane(m);
+        }
+        if (valid) {
+            const float s = (SHIFT && a.sxor) ? genz_pixel<SK, NUS, SHIFT, BACK, true>(K, a, p, n, nmax)
+                                              : genz_pixel<SK, NUS, SHIFT, BACK, false>(K, a, p, n, nmax);
+            write_pixel_n(a, p, s, N);
         }
     }
 }
@@ -1758,11 +1728,11 @@ __global__ __launch_bounds__(256) void scan_add(uint64_t* __restrict__ offsets, 
 // -------------------------------------------------------------------- host ----
 
 // Workspace: the task queues (kQueueBytes), then for the adjoint the exact accumulator, or for the
-// Genz forward pass the Sobol' tables (8 KB), the buckets' totals (256 bytes), per-wavefront
-// counts, the list of small pixels and the list of tiles with big pixels.
+// Genz forward pass the Sobol' tables (4 KB), the bucket sizes (512 bytes), the per-wavefront
+// counts and the pixel list.
 struct Plan {
-    size_t queue_off = 0, acc_off = kQueueBytes, tab_off = kQueueBytes, total_off = kQueueBytes + 8192,
-           wave_off = kQueueBytes + 8192 + 256, list_off = 0, tiles_off = 0, total = kQueueBytes;
+    size_t queue_off = 0, acc_off = kQueueBytes, tab_off = kQueueBytes, total_off = kQueueBytes + 4096,
+           wave_off = kQueueBytes + 4096 + 512, list_off = 0, total = kQueueBytes;
     uint32_t num_tasks = 0, n_theta = 0, n_row = 0, bucket_waves = 0;
     uint64_t acc_words = 0;
 };
@@ -1778,10 +1748,9 @@ Plan make_plan(const qmc_integrand* ig, uint32_t P, int mode) {
         pl.total = pl.acc_off + pl.acc_words * 8;
     } else if (ig && ig->kind == QMC_F_GENZ) {
         auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-        pl.bucket_waves = (pl.num_tasks + kBucketTiles - 1) / kBucketTiles;
-        pl.list_off = pl.wave_off + up(size_t(kWave) * pl.bucket_waves * 4);
-        pl.tiles_off = pl.list_off + up(size_t(P) * 4);
-        pl.total = pl.tiles_off + up(size_t(pl.num_tasks) * 4);
+        pl.bucket_waves = static_cast<uint32_t>((uint64_t(P) + kBucketPixels - 1) / kBucketPixels);
+        pl.list_off = pl.wave_off + up(size_t(kBuckets) * pl.bucket_waves * 4);
+        pl.total = pl.list_off + up(size_t(P) * 4);
     }
     return pl;
 }
@@ -2008,11 +1977,10 @@ qmc_status integrate_common(const char* who, qmc_context ctx, qmc_stream stream,
     a.bucket_total = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.total_off);
     a.bucket_wave = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.wave_off);
     a.bucket_list = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.list_off);
-    a.big_tiles = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.tiles_off);
     a.genz_tab = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + pl.tab_off);
     a.bucket_waves = pl.bucket_waves;
     const bool genz = !backward && ig->kind == QMC_F_GENZ;
-    // the Genz pass runs a task per tile with big pixels and per 64 small pixels
+    // the Genz pass runs a task per 64 pixels of a bucket (at most tiles + buckets tasks)
     const uint32_t grid = persistent_grid(ctx, integrate_tune(ctx, ig->kind, ig->d, backward),
                                           genz ? 2 * pl.num_tasks : pl.num_tasks, &a);
     const bool nus = (sp->flags & QMC_PIXEL_NUS) != 0, shift = (sp->flags & QMC_PIXEL_SHIFT) != 0;
@@ -2026,7 +1994,7 @@ qmc_status integrate_common(const char* who, qmc_context ctx, qmc_stream stream,
     if (genz) {
         const uint32_t bblocks = (pl.bucket_waves + kWavesPerBlock - 1) / kWavesPerBlock;
         hipLaunchKernelGGL(genz_bucket_count, dim3(bblocks), dim3(256), 0, hs, a);
-        hipLaunchKernelGGL(genz_bucket_scan, dim3(kWave), dim3(1024), 0, hs, a);
+        hipLaunchKernelGGL(genz_bucket_scan, dim3(kBuckets), dim3(1024), 0, hs, a);
         hipLaunchKernelGGL(genz_bucket_fill, dim3(bblocks), dim3(256), 0, hs, a);
     }
     if (!backward) {
