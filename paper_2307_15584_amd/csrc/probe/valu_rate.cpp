@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -86,17 +87,98 @@ __global__ __launch_bounds__(1024) void issue(uint32_t* sink, uint32_t seed) {
     if (x == 0x12345678u) sink[0] = x;
 }
 
+// The inner step of the lobe integrand: t = y s + b, e += t t for 32 dimensions, with y, s and
+// b in 96 distinct registers (each FMA reads three registers) and C exponent chains taking the
+// dimensions in turn, so that consecutive updates of one chain are 2C instructions apart.
+// 64 instructions per step.
+constexpr int kLobeDims = 32;
+constexpr int kLobeIters = kIters * kUnroll * kChains / (2 * kLobeDims);
+
+template <int C>
+__device__ __forceinline__ void lobe_group(float (&e)[C], const float* y, const float* s, const float* b);
+template <>
+__device__ __forceinline__ void lobe_group<1>(float (&e)[1], const float* y, const float* s, const float* b) {
+    float t0;
+    asm volatile("v_fma_f32 %0, %2, %3, %4\n\tv_fmac_f32 %1, %0, %0" : "=&v"(t0), "+v"(e[0]) : "v"(y[0]), "v"(s[0]), "v"(b[0]));
+}
+template <>
+__device__ __forceinline__ void lobe_group<2>(float (&e)[2], const float* y, const float* s, const float* b) {
+    float t0, t1;
+    asm volatile(
+        "v_fma_f32 %0, %4, %5, %6\n\tv_fma_f32 %1, %7, %8, %9\n\t"
+        "v_fmac_f32 %2, %0, %0\n\tv_fmac_f32 %3, %1, %1"
+        : "=&v"(t0), "=&v"(t1), "+v"(e[0]), "+v"(e[1])
+        : "v"(y[0]), "v"(s[0]), "v"(b[0]), "v"(y[1]), "v"(s[1]), "v"(b[1]));
+}
+template <>
+__device__ __forceinline__ void lobe_group<4>(float (&e)[4], const float* y, const float* s, const float* b) {
+    float e01[2] = {e[0], e[1]}, e23[2] = {e[2], e[3]};
+    float t0, t1, t2, t3;
+    asm volatile(
+        "v_fma_f32 %0, %8, %9, %10\n\tv_fma_f32 %1, %11, %12, %13\n\t"
+        "v_fma_f32 %2, %14, %15, %16\n\tv_fma_f32 %3, %17, %18, %19\n\t"
+        "v_fmac_f32 %4, %0, %0\n\tv_fmac_f32 %5, %1, %1\n\t"
+        "v_fmac_f32 %6, %2, %2\n\tv_fmac_f32 %7, %3, %3"
+        : "=&v"(t0), "=&v"(t1), "=&v"(t2), "=&v"(t3), "+v"(e01[0]), "+v"(e01[1]), "+v"(e23[0]), "+v"(e23[1])
+        : "v"(y[0]), "v"(s[0]), "v"(b[0]), "v"(y[1]), "v"(s[1]), "v"(b[1]),
+          "v"(y[2]), "v"(s[2]), "v"(b[2]), "v"(y[3]), "v"(s[3]), "v"(b[3]));
+    e[0] = e01[0];
+    e[1] = e01[1];
+    e[2] = e23[0];
+    e[3] = e23[1];
+}
+
+template <int C>
+__global__ __launch_bounds__(1024) void issue_lobe(uint32_t* sink, uint32_t seed) {
+    float y[kLobeDims], s[kLobeDims], b[kLobeDims];
+#pragma unroll
+    for (int j = 0; j < kLobeDims; ++j) {
+        y[j] = float(threadIdx.x + j) * 0x1p-10f;
+        s[j] = float(seed + j) * 0x1p-12f;
+        b[j] = -float(seed ^ j) * 0x1p-14f;
+    }
+    float e[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) e[c] = 0.0f;
+    __syncthreads();
+    for (int it = 0; it < kLobeIters; ++it) {
+#pragma unroll
+        for (int j = 0; j < kLobeDims; j += C) lobe_group<C>(e, y + j, s + j, b + j);
+    }
+    float x = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) x += e[c];
+    if (x == 1.2345f) sink[0] = 1u;
+}
+
+template <int C>
+struct LobeStep {
+    static constexpr int chains = C;
+    static constexpr const char* label = C == 1 ? "lobe step, 1 exponent chain (`v_fma_f32 t, y, s, b` + `v_fmac_f32 e, t, t`)"
+                                       : C == 2 ? "lobe step, 2 exponent chains" : "lobe step, 4 exponent chains";
+};
+template <typename T>
+struct IsLobe : std::false_type {};
+template <int C>
+struct IsLobe<LobeStep<C>> : std::true_type {};
+
 template <typename Op>
 void measure(int cus, int waves_per_simd, size_t lds, uint32_t* d_sink) {
     const int blocks = cus;                  // one block per compute unit
     const int threads = 256 * waves_per_simd;  // waves_per_simd wavefronts on each of the 4 SIMDs
-    hipLaunchKernelGGL(issue<Op>, dim3(blocks), dim3(threads), lds, 0, d_sink, 12345u);  // warm-up
+    auto launch = [&](uint32_t seed) {
+        if constexpr (IsLobe<Op>::value)
+            hipLaunchKernelGGL(issue_lobe<Op::chains>, dim3(blocks), dim3(threads), lds, 0, d_sink, seed);
+        else
+            hipLaunchKernelGGL(issue<Op>, dim3(blocks), dim3(threads), lds, 0, d_sink, seed);
+    };
+    launch(12345u);  // warm-up
     CHECK(hipDeviceSynchronize());
     hipEvent_t e0, e1;
     CHECK(hipEventCreate(&e0));
     CHECK(hipEventCreate(&e1));
     CHECK(hipEventRecord(e0));
-    hipLaunchKernelGGL(issue<Op>, dim3(blocks), dim3(threads), lds, 0, d_sink, 777u);
+    launch(777u);
     CHECK(hipEventRecord(e1));
     CHECK(hipEventSynchronize(e1));
     CHECK(hipGetLastError());
@@ -139,6 +221,9 @@ int main(int argc, char** argv) {
     measure<CvtF32U32>(cus, wps, lds, d_sink);
     measure<ExpF32>(cus, wps, lds, d_sink);
     measure<CosF32>(cus, wps, lds, d_sink);
+    measure<LobeStep<1>>(cus, wps, lds, d_sink);
+    measure<LobeStep<2>>(cus, wps, lds, d_sink);
+    measure<LobeStep<4>>(cus, wps, lds, d_sink);
     CHECK(hipFree(d_sink));
     return 0;
 }
