@@ -1150,6 +1150,38 @@ __global__ __launch_bounds__(256) void genz_bucket_fill(Args a) {
     }
 }
 
+// Materialised samples of a task's pixels with 64 or more samples: the wavefront takes the pixels
+// one at a time, a lane per sample, so that each load instruction reads 256 consecutive bytes of a
+// dimension (one lane per pixel reads eight dimension rows per pixel, 512 scattered streams per
+// wavefront).  The values are summed in sample order, one lane's value after the other, so the
+// result equals the generating paths' bit for bit.
+__device__ void genz_points_by_pixel(const Args& a, uint32_t p, uint32_t n, uint32_t N, bool valid) {
+    const uint32_t lane = lane_id();
+    uint64_t todo = __ballot(valid);
+    while (todo) {
+        const uint32_t r = static_cast<uint32_t>(__builtin_ctzll(todo));
+        todo &= todo - 1;
+        const uint32_t pr = __builtin_amdgcn_readlane(p, r);
+        const uint32_t nr = __builtin_amdgcn_readlane(n, r);
+        const uint32_t Nr = __builtin_amdgcn_readlane(N, r);
+        GenzPixel gp;
+        gp.load<false>(a, pr);
+        const float* base = a.points + a.offsets[pr] + a.begin;
+        float acc = 0.0f;
+        for (uint32_t k0 = 0; k0 < nr; k0 += kWave) {
+            const uint32_t k = k0 + lane;
+            float X[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) X[j] = k < nr ? base[uint64_t(j) * a.points_ld + k] : 0.0f;
+            const float f = gp.eval(X);
+            const uint32_t cnt = min(kWave, nr - k0);
+            for (uint32_t t = 0; t < cnt; ++t)
+                acc = add_nc(acc, __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(f), t)));
+        }
+        if (lane == 0) write_pixel_n(a, pr, acc, Nr);
+    }
+}
+
 template <uint32_t SK, bool NUS, bool SHIFT, bool BACK>
 __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
     // Task table in processing order (position q holds bucket 89 - q): first chunk and first list
@@ -1194,6 +1226,12 @@ __global__ __launch_bounds__(kBlock) void genz_fwd(Args a) {
         const uint32_t N = valid ? a.counts[p] : 0u;
         const uint32_t n = valid ? window_count(a, N) : 0u;
         const uint32_t b = kBuckets - 1 - q;
+        if constexpr (SK == QMC_SAMPLER_POINTS) {
+            if (b >= kWave) {
+                genz_points_by_pixel(a, p, n, N, valid);
+                continue;
+            }
+        }
         // exact counts below 64; above, the task steps to its largest count
         uint32_t nmax = b;
         if (b >= kWave) {
