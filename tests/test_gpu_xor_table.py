@@ -98,6 +98,36 @@ def test_genz_forward_and_plain_equals_fused(qmc):
     assert np.array_equal(got.view(np.uint32), plain.view(np.uint32))
 
 
+@pytest.mark.parametrize("N", [256, 2])
+@pytest.mark.parametrize("begin,end", [(3, 200), (1, 2), (5, 9), (64, 1000), (6, 2**32 - 1)])
+def test_genz_sample_windows(qmc, N, begin, end):
+    """Windows [begin, end) whose start is not a multiple of four: the fused kernel reads the stored
+    points of an aligned group of four samples at once (N >= 4) and takes the samples before the
+    first group, and after the last, one at a time; N = 2 takes every sample one at a time.  The
+    plain path over the materialised samples of the same window equals the fused one bit for bit
+    (pixels with 64 or more samples in the window read a lane per sample, the others a lane per
+    pixel)."""
+    import torch
+
+    W, H = 131, 4
+    P = W * H
+    counts = _counts_edge(P)
+    ds, os_ = _pair(qmc, 8, N, 5, W)
+    pp = genz_params(P, 4)
+    ig = qmc.PixelIntegrand.genz(torch.from_numpy(pp).cuda())
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    got = qmc.qmc_integrate_pixels(ds, ig, W, H, dc, begin, end)
+    offs = qmc.qmc_sample_offsets(dc)
+    pts = qmc.qmc_generate_pixel_samples(ds, 8, W, H, dc, offs, int(counts.astype(np.int64).sum()))
+    plain = qmc.qmc_integrate_pixels(qmc.PixelSampler.points(pts, offs), ig, W, H, dc, begin, end)
+    torch.cuda.synchronize()
+    got, plain = got.cpu().numpy(), plain.cpu().numpy()
+    ref = estimator.integrate_pixels(os_, {"kind": "genz", "d": 8, "pixel_params": pp}, counts, range(P), begin, end)
+    ok = _est_tol(got, ref)
+    assert ok.all(), (np.nonzero(~ok)[0][:10], got[~ok][:5], ref["mean"][~ok][:5])
+    assert np.array_equal(got.view(np.uint32), plain.view(np.uint32))
+
+
 @pytest.mark.parametrize("d,L,W,H,N", [(8, 64, 131, 2, 128), (40, 7, 3, 130, 64)])
 def test_lobes_forward(qmc, d, L, W, H, N):
     import torch
