@@ -62,7 +62,7 @@ GENZ_CASES = [
     ("sobol", NUS | SHIFT | XOR, 37, 11, "edge", 0, 2**32 - 1),     # ragged last tile, all size classes
     ("sobol", 0, 40, 8, "edge", 0, 2**32 - 1),                      # unscrambled
     ("sobol", SHIFT, 40, 8, "edge", 64, 200),                       # window, aligned start
-    ("sobol", NUS, 40, 8, "edge", 37, 150),                         # window, unaligned start (general path)
+    ("sobol", NUS, 40, 8, "edge", 37, 150),                         # window, unaligned start
     ("lattice", SHIFT, 48, 20, "pow2", 0, 2**32 - 1),
     ("lattice", SHIFT | BACK | XOR, 37, 11, "edge", 0, 2**32 - 1),
 ]
