@@ -969,7 +969,37 @@ __device__ __forceinline__ float genz_pixel(const GenzKeys& K, const Args& a, ui
 #pragma unroll
         for (int j = 0; j < 8; ++j) h[j] = sload(a.genz_tab + kTabH0 + j);
     }
-    for (uint32_t k = 0; k < nmax; ++k) {
+    uint32_t k0 = 0;
+    if constexpr (SK == QMC_SAMPLER_SOBOL) {
+        // two samples per step: both index parts first (scalar work and its branch), then the two
+        // samples' vector work in one block
+        for (; k0 + 2 <= nmax; k0 += 2) {
+            uint32_t ipa[8], ipb[8];
+            const uint32_t i = a.begin + k0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) ipa[j] = h[j] ^ sload(a.genz_tab + kTabT + (i & 63u) * 8 + j);
+            if (((i + 1u) & 63u) == 0u) {
+                const uint32_t t = min(static_cast<uint32_t>(__builtin_ctz((i + 1u) >> 6)), kQI - 1);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) h[j] ^= sload(a.genz_tab + kTabQ + t * 8 + j);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) ipb[j] = h[j] ^ sload(a.genz_tab + kTabT + ((i + 1u) & 63u) * 8 + j);
+            if (((i + 2u) & 63u) == 0u) {
+                const uint32_t t = min(static_cast<uint32_t>(__builtin_ctz((i + 2u) >> 6)), kQI - 1);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) h[j] ^= sload(a.genz_tab + kTabQ + t * 8 + j);
+            }
+            float Xa[8], Xb[8];
+            genz_sample<SK, NUS, SHIFT, BACK, SX, 0>(Xa, g, K, a, i, ipa, true);
+            genz_sample<SK, NUS, SHIFT, BACK, SX, 0>(Xb, g, K, a, i + 1u, ipb, true);
+            const float fa = gp.eval(Xa);
+            const float fb = gp.eval(Xb);
+            if (k0 < n) acc = add_nc(acc, fa);
+            if (k0 + 1 < n) acc = add_nc(acc, fb);
+        }
+    }
+    for (uint32_t k = k0; k < nmax; ++k) {
         const uint32_t i = a.begin + k;
         uint32_t ip[8];
         if constexpr (SK == QMC_SAMPLER_SOBOL) {
