@@ -239,6 +239,10 @@ def test_autotune_generate_reports_candidates(qmc):
     ("lattice", 40, 64 * 3, 3000, XOR, 41),     # two groups of dimensions
     ("sobol", 40, 64 * 5, 2000, XOR, 44),       # 16-byte rows: vector stores, then a group of 8
     ("lattice", 36, 0, 1500, XOR, 36),
+    # multiples of 32 dimensions with 16-byte rows
+    ("sobol", 64, 64 * 77, 4133, XOR, 68),       # two chunks, ragged last tile, gaps between rows
+    ("sobol", 32, (1 << 32) - 64 * 50, 64 * 50, 0, 36),   # top of the index range
+    ("lattice", 64, 5, 4133, XOR | BACK, 64),
 ])
 def test_point_major_layout(qmc, kind, s, first, n, flags, ld):
     """out[(i - first) * ld + j] against the oracle, bit for bit, and nothing written between
@@ -268,13 +272,15 @@ def test_point_major_layout(qmc, kind, s, first, n, flags, ld):
         assert (gu[:, s:] == 7).all() and (out_f[:, s:] == 2.0).all().item()
 
 
-def test_point_major_many_tiles_per_wavefront(qmc):
+@pytest.mark.parametrize("s", [33, 64])
+def test_point_major_many_tiles_per_wavefront(qmc, s):
     """More 64-point tiles than wavefronts (each wavefront loops over several, unevenly) with two
-    groups of dimensions (s = 33): 3000 sampled points against the oracle, whole rows, for the
-    Sobol' and the lattice generator."""
+    groups of dimensions (s = 33: 4-byte stores for the second; s = 64: 16-byte stores for both):
+    3000 sampled points against the oracle, whole rows, for the Sobol' and the lattice
+    generator."""
     import torch
 
-    s, first, n = 33, 64 * 7, (1 << 21) + 37
+    first, n = 64 * 7, (1 << 21) + 37
     m = _mats(s)
     seeds, shifts = nus_seeds(s, 1), cp_shifts(s, 2)
     out_u = torch.empty((n, s), dtype=torch.int32, device="cuda")
