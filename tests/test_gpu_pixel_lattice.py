@@ -90,6 +90,26 @@ def test_genz_estimates_and_windows(qmc, flags):
     assert _est_tol(got.astype(np.float32), ref).all()
 
 
+@pytest.mark.parametrize("flags", [RGEN | INST4 | SHIFT, HIL | BACK])
+@pytest.mark.parametrize("begin,end", [(3, 70), (1, 2), (130, 2 ** 32 - 1)])
+def test_genz_unaligned_windows(qmc, flags, begin, end):
+    """Windows whose first sample is not instance 0 of the four superimposed instances (nor on a
+    multiple of 64): window sums against the oracle's over the same samples."""
+    import torch
+
+    W, H = 37, 11
+    P = W * H
+    counts = counts_pow2(W, H, 5)
+    pp = genz_params(P, 4)
+    ds, os_ = _pair(qmc, 8, 77, flags, W, H)
+    ig = qmc.PixelIntegrand.genz(torch.from_numpy(pp).cuda())
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    means = qmc.qmc_integrate_pixels(ds, ig, W, H, dc, begin, end)
+    torch.cuda.synchronize()
+    ref = estimator.integrate_pixels(os_, {"kind": "genz", "d": 8, "pixel_params": pp}, counts, range(P), begin, end)
+    assert _est_tol(means.cpu().numpy(), ref).all()
+
+
 @pytest.mark.parametrize("d,L,W,H,cname,flags", [(8, 64, 40, 8, "64", HIL | SHIFT), (8, 10, 23, 5, "edge", RGEN | INST4),
                                                    (64, 32, 6, 4, "64", HIL | RGEN)])
 def test_lobes_fused_step_against_oracle(qmc, d, L, W, H, cname, flags):
