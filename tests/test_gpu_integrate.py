@@ -97,7 +97,7 @@ LOBE_CASES = [
     (5, 70, "edge", 21, 4, "sobol", NUS | SHIFT),          # d < 8, more lobes than one group
     (64, 32, "64", 8, 4, "sobol", NUS | SHIFT),            # two 32-dim halves per lobe
     (20, 7, "edge", 9, 3, "lattice", SHIFT | BACK),
-    (50, 45, "edge", 7, 5, "sobol", NUS | SHIFT),          # d > 32: quarters of 16 dims, two lobe groups
+    (50, 45, "edge", 7, 5, "sobol", NUS | SHIFT),          # d > 32 (14 unused dims of 64), two lobe groups
     (40, 33, "64", 5, 3, "lattice", SHIFT),                # one lobe in the second group
 ]
 
@@ -116,6 +116,32 @@ def test_lobes_forward_matches_fp64_oracle(qmc, case):
     got = qmc.qmc_integrate_pixels(ds, ig, W, H, dc).cpu().numpy()
     ref = estimator.integrate_pixels(os_, {"kind": "lobes", "d": d, "num_lobes": L, "params": theta,
                                            "pixel_seed": 5}, counts, range(P))
+    ok = _est_tol(got, ref)
+    assert ok.all(), (np.nonzero(~ok)[0][:10], got[~ok][:5], ref["mean"][~ok][:5])
+
+
+@pytest.mark.parametrize("d,L,kind,flags,begin,end", [
+    (8, 64, "sobol", NUS | SHIFT, 37, 150),      # window off a multiple of 64: index parts by the matrix
+    (64, 32, "sobol", NUS | SHIFT, 37, 150),
+    (64, 32, "sobol", NUS | SHIFT, 64, 300),     # on a multiple of 64: per-round index parts
+    (64, 32, "lattice", SHIFT | BACK, 3, 200),
+    (40, 7, "sobol", NUS, 128, 2**32 - 1),
+])
+def test_lobes_forward_windows(qmc, d, L, kind, flags, begin, end):
+    """Lobe estimates over sample windows (the progressive passes' building block) against the
+    oracle's sums over the same samples."""
+    import torch
+
+    W, H = 13, 5
+    P = W * H
+    counts = _counts_edge(P)
+    theta, dtheta = _lobes_setup(qmc, L, d)
+    ds, os_ = _sampler_pair(qmc, kind, max(d, 8), 77, flags)
+    ig = qmc.PixelIntegrand.lobes(dtheta, L, d, 5)
+    dc = torch.from_numpy(counts.view(np.int32)).cuda()
+    got = qmc.qmc_integrate_pixels(ds, ig, W, H, dc, begin, end).cpu().numpy()
+    ref = estimator.integrate_pixels(os_, {"kind": "lobes", "d": d, "num_lobes": L, "params": theta,
+                                           "pixel_seed": 5}, counts, range(P), begin, end)
     ok = _est_tol(got, ref)
     assert ok.all(), (np.nonzero(~ok)[0][:10], got[~ok][:5], ref["mean"][~ok][:5])
 
